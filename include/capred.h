@@ -1,0 +1,266 @@
+/*
+ * capred.h -- C ABI of the MI355X (gfx950) confidence-aware particle
+ * prediction library (libcapred.so).
+ *
+ * Method: Lu, Bui, Lyu, Chen, "Fast Confidence-Aware Human Prediction via
+ * Hardware-accelerated Bayesian Inference for Safe Robot Navigation".
+ *   - belief over (rationality beta, goal g) updated from observed steps by
+ *     Bayes' rule, Eq. (beta_update), in the log form of Sec. III-B;
+ *   - Boltzmann heading policy pi(u|z;beta,g) ~ exp(beta Q(z,u;g)),
+ *     Eq. (human_softmax_policy), with Q = -|z + v dt u - g|;
+ *   - Alg. 1: particles draw (beta,g) once from the belief, roll H steps of
+ *     the discretised kinematic model (Eq. human_dynamics) with Boltzmann
+ *     headings, and are emplaced per step on occupancy grids.
+ *
+ * Conventions shared by every call:
+ *   headings      theta_k = 2 pi k / K, counter-clockwise from +x, fixed speed.
+ *   pair index    j = g * B + b; beliefs are FP64 arrays laid out [G][B].
+ *   lattice       prediction state is int32 on a lattice of pitch q = cell/2^16
+ *                 from the grid origin; steps S_k = rint(v dt (cos,sin)theta_k / q);
+ *                 start and goals are rounded with rint((z - origin)/q).
+ *   cells         cell = floor(X / 2^16); grid t (1..H) holds positions after t steps.
+ *   random draws  Philox4x32-10, key (seed lo, seed hi), uniform
+ *                 u = (2 (w >> 9) + 1) 2^-24:
+ *                   pair      counter (i, 0,       human, 2 cycle)     word 0
+ *                   heading t counter (i, (t-1)/4, human, 2 cycle + 1) word (t-1)%4
+ *                   simulated track n, step t: counter (n, (t-1)/4, stream, 0xFFFFFFFF)
+ *   inverse CDF   heading k = min{k : u C_{K-1} < C_k} (else K-1); pair j = min{j :
+ *                 u < P_j} over the sequential FP64 prefix sums P (else the last
+ *                 j with positive belief).
+ *
+ * Memory: every pointer named *_dev is device memory owned by the caller; host
+ * pointers are read during the call only.  No call allocates device memory
+ * except cap_plan_create (descriptors, owned by the plan).  Every call is
+ * asynchronous on the caller's stream (a hipStream_t passed as void*; NULL is
+ * the null stream) and never synchronises it.  Calls return a cap_status and
+ * never throw; cap_last_error() gives a thread-local message for the last
+ * failure.
+ */
+#ifndef CAPRED_H
+#define CAPRED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CAP_ABI_VERSION 1
+#define CAP_MAX_K 32   /* headings per model                       */
+#define CAP_MAX_B 16   /* rationality values per model             */
+#define CAP_MAX_G 64   /* goals per model                          */
+#define CAP_MAX_J 512  /* (beta, g) pairs, G * B                    */
+
+typedef enum cap_status {
+  CAP_OK = 0,
+  CAP_E_INVALID = -1,     /* an argument is out of range or a required pointer is NULL */
+  CAP_E_HIP = -2,         /* a HIP runtime call failed (message in cap_last_error)    */
+  CAP_E_WORKSPACE = -3,   /* the workspace is NULL or smaller than required             */
+  CAP_E_UNSUPPORTED = -4, /* no gfx950 device or a feature not built in                 */
+  CAP_E_CAPACITY = -5     /* a plan has no room (slots, particles, grid cells)           */
+} cap_status;
+
+/* Human model (Sec. III-A).  Host memory. */
+typedef struct cap_model {
+  int32_t K;            /* headings, 2..CAP_MAX_K                                   */
+  double speed;         /* walking speed v in m/s, > 0                              */
+  double dt;            /* prediction / observation step in s, > 0                  */
+  int32_t B;            /* rationality values, 1..CAP_MAX_B                         */
+  const float* beta;    /* host [B], every value > 0                                */
+  int32_t G;            /* goals, 1..CAP_MAX_G, with G * B <= CAP_MAX_J             */
+  const float* goals;   /* host [G][2], metres, world frame                         */
+} cap_model;
+
+/* Occupancy grid: nx * ny cells of side `cell` metres, lower-left corner at
+ * (x0, y0).  1 <= nx, ny <= 16384. */
+typedef struct cap_grid {
+  double x0, y0, cell;
+  int32_t nx, ny;
+} cap_grid;
+
+/* Library / device queries. */
+int32_t cap_abi_version(void);
+const char* cap_last_error(void);
+/* Number of compute units of the current device (0 on failure). */
+int32_t cap_device_cu_count(void);
+
+/* ------------------------------------------------------------------------
+ * Belief update, Eq. (beta_update) in log space (Sec. III-B):
+ *   for each observed transition (z_t, z_{t+1}) the heading is recovered as
+ *   k* = argmax_k <z_{t+1} - z_t, (cos, sin) theta_k> (lowest k on ties;
+ *   a transition shorter than 1e-9 m is skipped), and
+ *   log b(beta,g) += sum_t log pi(k*_t | z_t; beta, g),
+ *   followed by one log-sum-exp renormalisation over all (beta, g) in FP64.
+ * The policy terms are FP32 (continuous steps fl32(v dt (cos,sin) theta_k)),
+ * accumulated in FP64.
+ *   obs_dev         [n_obs + 1][2] FP32 metres, n_obs >= 0
+ *   log_belief_dev  [G][B] FP64, in: prior (log), out: posterior (log);
+ *                   entries may be -inf (pairs ruled out).
+ *   belief_dev      [G][B] FP64 out: exp(log posterior); may be NULL.
+ * Errors: CAP_E_INVALID for a bad model, n_obs < 0, NULL obs (n_obs > 0) or NULL
+ * log_belief. */
+cap_status cap_belief_update(const cap_model* model, const float* obs_dev, int32_t n_obs,
+                             double* log_belief_dev, double* belief_dev, void* stream);
+
+/* Uniform prior b^1 = 1 / (|B| |G|) (Sec. III-B) written to log_belief_dev [G][B]. */
+cap_status cap_belief_reset(int32_t G, int32_t B, double* log_belief_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Alg. 1 for one human: N particles start at z0 (host, metres), each draws
+ * (beta, g) from belief_dev once (bootstrapped belief, Sec. III-B) and takes H
+ * Boltzmann heading steps; grid t receives the particles after t steps.
+ *   belief_dev   [G][B] FP64, non-negative, summing to 1 (not renormalised).
+ *   counts_dev   [H][ny][nx] uint32 out; zeroed by the call.
+ *   offgrid_dev  [H] uint32 out (particles outside the grid), zeroed; may be NULL.
+ *   trace_k_dev  [N][H] uint8 out, chosen heading per step; may be NULL.
+ *   trace_pair_dev [N] int32 out, pair index j per particle; may be NULL.
+ *   1 <= N <= 2^30, 1 <= H <= 4096, cycle < 2^31 - 1.
+ * Errors: CAP_E_INVALID for a bad model/grid/size, a start or goal whose
+ * lattice coordinates (plus H steps) leave the int32 range, or a step shorter
+ * than 2 lattice units. */
+cap_status cap_predict_occupancy(const cap_model* model, const cap_grid* grid,
+                                 const double z0[2], const double* belief_dev, int32_t N,
+                                 int32_t H, uint64_t seed, uint32_t human_id, uint32_t cycle,
+                                 uint32_t* counts_dev, uint32_t* offgrid_dev,
+                                 uint8_t* trace_k_dev, int32_t* trace_pair_dev, void* stream);
+
+/* Occupancy probabilities p = (float)count / (float)N (IEEE FP32 division),
+ * the output p(z_{t'+t} | z_{1:t'}) of Alg. 1.
+ *   counts_dev [n_cells] uint32, probs_dev [n_cells] FP32; N >= 1. */
+cap_status cap_normalize(const uint32_t* counts_dev, int64_t n_cells, int32_t N,
+                         float* probs_dev, void* stream);
+
+/* Raw Philox4x32-10 blocks of the library's generator, for counters
+ * (c0 + i, c1, c2, c3), i < n, key (seed lo, seed hi): out_dev [n][4] uint32.
+ * Exposed so that the random-number contract above can be checked directly. */
+cap_status cap_philox_blocks(int64_t n, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                             uint64_t seed, uint32_t* out_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Synthetic humans: n tracks of T lattice steps, each following the Boltzmann
+ * policy with its own fixed (beta, goal) (the model of Sec. III-A, used as a
+ * simulator).  The lattice frame (x0, y0, cell) fixes q.
+ *   start_dev [n][2] FP64 metres, beta_dev [n] FP32, goal_dev [n][2] FP32 metres.
+ *   lat_dev   [n][T+1][2] int32 lattice positions out (may be NULL).
+ *   pos_dev   [n][T+1][2] FP32 metres out: fl32(origin + X q) (may be NULL). */
+cap_status cap_simulate_tracks(int32_t K, double speed, double dt, double x0, double y0,
+                               double cell, int32_t n, int32_t T, const double* start_dev,
+                               const float* beta_dev, const float* goal_dev, uint64_t seed,
+                               uint32_t stream_id, int32_t* lat_dev, float* pos_dev,
+                               void* stream);
+
+/* ------------------------------------------------------------------------
+ * Trajectory log-likelihood over tracks (product form of Eq. beta_update,
+ * unnormalised):  LL[n][b][g] = sum_{t < len_n} log pi(k*_t | z_t; exp(log_beta), g)
+ *   tracks_dev   [N][Tmax+1][2] FP32 metres; lengths_dev [N] int32 in [0, Tmax].
+ *   goals_dev    [G][2] FP32 metres (continuous, differentiable).
+ *   log_beta_dev [B] FP32, or [N][B] when per_track_beta != 0.
+ *   LL_dev       [N][B][G] FP64 out.
+ * FP32 policy terms, FP64 sums over t.  No workspace. */
+cap_status cap_loglik(int32_t K, double speed, double dt, const float* tracks_dev,
+                      const int32_t* lengths_dev, int32_t N, int32_t Tmax,
+                      const float* goals_dev, int32_t G, const float* log_beta_dev, int32_t B,
+                      int32_t per_track_beta, double* LL_dev, void* stream);
+
+/* Adjoint of cap_loglik: given dLL_dev [N][B][G] FP64,
+ *   dgoals_dev   [G][2] FP64 = sum_{n,b,t} dLL * beta (yhat_{k*} - E_p[yhat]),
+ *   dlog_beta_dev [B] (or [N][B]) FP64 = sum_{n,g,t} dLL * (-beta)(d_{k*} - E_p[d]),
+ * with d_k = |z_t + s_k - g|, yhat_k = (z_t + s_k - g)/d_k, p = pi(.|z_t).
+ * Reductions are FP64 and deterministic (fixed-order two-stage sums through
+ * the workspace; no floating-point atomics).
+ *   ws_dev / ws_bytes: workspace of at least cap_loglik_backward_workspace(...) bytes. */
+cap_status cap_loglik_backward(int32_t K, double speed, double dt, const float* tracks_dev,
+                               const int32_t* lengths_dev, int32_t N, int32_t Tmax,
+                               const float* goals_dev, int32_t G, const float* log_beta_dev,
+                               int32_t B, int32_t per_track_beta, const double* dLL_dev,
+                               double* dgoals_dev, double* dlog_beta_dev, void* ws_dev,
+                               size_t ws_bytes, void* stream);
+size_t cap_loglik_backward_workspace(int32_t N, int32_t G, int32_t B, int32_t per_track_beta);
+
+/* ------------------------------------------------------------------------
+ * Batched many-human prediction: one persistent launch per cycle for all
+ * humans (replacing the sequential per-human loop of Sec. IV-B), captured in
+ * hipGraphs together with the belief update, the grid clear and the
+ * normalisation.  A plan has `n_slots` slots sharing one model family (K,
+ * speed, dt); each slot holds one human with its own N, H, goals, beta grid,
+ * grid geometry and output buffers.  Slots are filled and emptied between
+ * cycles (continuous batching) without re-capture: the graphs read compact
+ * per-cycle descriptors that cap_plan_run copies to the device.
+ *
+ * Cycles may overlap on the device: cycle c uses ring entry e = c % ring of
+ * every per-cycle buffer (descriptors, posterior, grids), and cap_plan_run
+ * waits on the host only when the entry it needs is still in flight.  Belief
+ * updates of consecutive cycles are ordered by an event even when the caller
+ * alternates streams.
+ *
+ * Results are keyed by the human id and cycle, never by the slot, so a human
+ * gets the same grids alone or in any mix. */
+typedef struct cap_plan cap_plan;
+
+typedef struct cap_plan_config {
+  int32_t n_slots;              /* 1..CAP_MAX_SLOTS                             */
+  int32_t K;                    /* headings (shared)                            */
+  double speed, dt;             /* shared                                       */
+  int32_t max_obs;              /* new observed positions per slot per cycle, 1..8 */
+  int32_t ring;                 /* per-cycle buffer ring depth, 1..4            */
+  int32_t block_threads;        /* 0 = default; else 256, 512 or 1024           */
+  int32_t particles_per_thread; /* 0 = default; else 1, 2 or 4                  */
+  int32_t lds_bytes;            /* 0 = default; LDS histogram window per block  */
+  int32_t grid_blocks;          /* 0 = default; persistent blocks per launch    */
+} cap_plan_config;
+
+#define CAP_MAX_SLOTS 256
+
+typedef struct cap_slot_desc {
+  uint32_t human_id;            /* stable id keying the random streams          */
+  int32_t N, H;                 /* particles (<= 2^30), horizon                 */
+  int32_t B;                    /* beta values                                  */
+  const float* beta;            /* host [B]                                     */
+  int32_t G;                    /* goals                                        */
+  const float* goals;           /* host [G][2] metres                           */
+  cap_grid grid;                /* per-human grid                               */
+  float last_xy[2];             /* last observed position before the first staged one */
+  uint32_t* counts_dev;         /* [ring][H][ny][nx] uint32, caller-owned       */
+  uint32_t* offgrid_dev;        /* [ring][H] uint32 or NULL                     */
+  float* probs_dev;             /* [ring][H][ny][nx] FP32 or NULL (skip normalisation) */
+  double* log_belief_dev;       /* [G][B] FP64 belief state, caller-owned, in/out */
+  double* belief_dev;           /* [ring][G][B] FP64 posterior out (read by the rollout) */
+  int32_t reset_belief;         /* 1: write the uniform prior before the first update */
+} cap_slot_desc;
+
+cap_status cap_plan_create(const cap_plan_config* cfg, cap_plan** out);
+void cap_plan_destroy(cap_plan* plan);
+/* Admit a human into an empty slot (validated like cap_predict_occupancy). */
+cap_status cap_plan_set_slot(cap_plan* plan, int32_t slot, const cap_slot_desc* desc);
+/* Retire the human in `slot`; its buffers are not touched by later cycles. */
+cap_status cap_plan_clear_slot(cap_plan* plan, int32_t slot);
+/* Stage the new observed positions of `slot` for the next cycle:
+ * xy [n_new][2] FP32 metres (host), 0 <= n_new <= max_obs.  The first one
+ * continues from the slot's last observed position. */
+cap_status cap_plan_stage_obs(cap_plan* plan, int32_t slot, const float* xy, int32_t n_new);
+/* Run one cycle on `stream`: copy the compact descriptors (with staged
+ * observations) to ring entry cycle % ring and launch the captured graphs:
+ * belief update -> grid clear -> persistent batched rollout -> normalisation.
+ * Every active slot is predicted from its newest observed position.  The
+ * staging area is reusable when this returns.  cycle < 2^31 - 1. */
+cap_status cap_plan_run(cap_plan* plan, uint64_t seed, uint32_t cycle, void* stream);
+/* Block the host until the last run has completed on the device. */
+cap_status cap_plan_sync(cap_plan* plan);
+/* Totals over the active slots: particles, particle-steps, rollout tiles. */
+cap_status cap_plan_stats(const cap_plan* plan, int64_t* particles, int64_t* particle_steps,
+                          int32_t* tiles);
+/* Effective tuning of the plan (after defaults are resolved). */
+cap_status cap_plan_tuning(const cap_plan* plan, cap_plan_config* out);
+
+/* Plain per-human reference of one serving cycle (the paper's sequential
+ * multi-human procedure, Sec. IV-B): for each active slot in turn, belief
+ * update -> clear -> single-human rollout -> normalisation, one launch each,
+ * on `stream`.  Same kernels' arithmetic and random keys as cap_plan_run, so
+ * the outputs are identical; used to measure the batched form against it. */
+cap_status cap_plan_run_plain(cap_plan* plan, uint64_t seed, uint32_t cycle, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAPRED_H */

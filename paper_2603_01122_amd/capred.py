@@ -1,0 +1,323 @@
+"""PyTorch binding of libcapred.so (the C ABI in include/capred.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the current stream.  The
+module raises ImportError when the library has not been built -- there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcapred.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2603_01122_amd.build.build() "
+                      "(hipcc for gfx950). There is no CPU fallback.")
+
+_lib = C.CDLL(LIB_PATH)
+
+CAP_OK, CAP_E_INVALID, CAP_E_HIP, CAP_E_WORKSPACE, CAP_E_UNSUPPORTED, CAP_E_CAPACITY = \
+    0, -1, -2, -3, -4, -5
+MAX_K, MAX_B, MAX_G, MAX_J, MAX_SLOTS = 32, 16, 64, 512, 256
+
+
+class CapError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = _lib.cap_last_error().decode()
+        super().__init__(f"{what} failed with status {status}: {msg}")
+        self.status = status
+
+
+class cap_model(C.Structure):
+    _fields_ = [("K", C.c_int32), ("speed", C.c_double), ("dt", C.c_double), ("B", C.c_int32),
+                ("beta", C.POINTER(C.c_float)), ("G", C.c_int32),
+                ("goals", C.POINTER(C.c_float))]
+
+
+class cap_grid(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("cell", C.c_double), ("nx", C.c_int32),
+                ("ny", C.c_int32)]
+
+
+class cap_plan_config(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("K", C.c_int32), ("speed", C.c_double),
+                ("dt", C.c_double), ("max_obs", C.c_int32), ("ring", C.c_int32),
+                ("block_threads", C.c_int32), ("particles_per_thread", C.c_int32),
+                ("lds_bytes", C.c_int32), ("grid_blocks", C.c_int32)]
+
+
+class cap_slot_desc(C.Structure):
+    _fields_ = [("human_id", C.c_uint32), ("N", C.c_int32), ("H", C.c_int32), ("B", C.c_int32),
+                ("beta", C.POINTER(C.c_float)), ("G", C.c_int32),
+                ("goals", C.POINTER(C.c_float)), ("grid", cap_grid),
+                ("last_xy", C.c_float * 2), ("counts_dev", C.c_void_p),
+                ("offgrid_dev", C.c_void_p), ("probs_dev", C.c_void_p),
+                ("log_belief_dev", C.c_void_p), ("belief_dev", C.c_void_p),
+                ("reset_belief", C.c_int32)]
+
+
+_vp, _i32, _u32, _u64, _i64, _d, _sz = (C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64,
+                                        C.c_int64, C.c_double, C.c_size_t)
+
+
+def _sig(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+_sig("cap_abi_version", _i32)
+_sig("cap_last_error", C.c_char_p)
+_sig("cap_device_cu_count", _i32)
+_sig("cap_belief_update", _i32, C.POINTER(cap_model), _vp, _i32, _vp, _vp, _vp)
+_sig("cap_belief_reset", _i32, _i32, _i32, _vp, _vp)
+_sig("cap_predict_occupancy", _i32, C.POINTER(cap_model), C.POINTER(cap_grid),
+     C.POINTER(C.c_double), _vp, _i32, _i32, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp)
+_sig("cap_normalize", _i32, _vp, _i64, _i32, _vp, _vp)
+_sig("cap_simulate_tracks", _i32, _i32, _d, _d, _d, _d, _d, _i32, _i32, _vp, _vp, _vp, _u64, _u32,
+     _vp, _vp, _vp)
+_sig("cap_loglik", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp)
+_sig("cap_loglik_backward", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _i32,
+     _vp, _vp, _vp, _vp, _sz, _vp)
+_sig("cap_loglik_backward_workspace", _sz, _i32, _i32, _i32, _i32)
+_sig("cap_philox_blocks", _i32, _i64, _u32, _u32, _u32, _u32, _u64, _vp, _vp)
+EXPORTED = ["cap_philox_blocks", "cap_abi_version", "cap_last_error", "cap_device_cu_count", "cap_belief_update",
+            "cap_belief_reset", "cap_predict_occupancy", "cap_normalize", "cap_simulate_tracks",
+            "cap_loglik", "cap_loglik_backward", "cap_loglik_backward_workspace"]
+if hasattr(_lib, "cap_plan_create"):
+    _sig("cap_plan_create", _i32, C.POINTER(cap_plan_config), C.POINTER(_vp))
+    _sig("cap_plan_destroy", None, _vp)
+    _sig("cap_plan_set_slot", _i32, _vp, _i32, C.POINTER(cap_slot_desc))
+    _sig("cap_plan_clear_slot", _i32, _vp, _i32)
+    _sig("cap_plan_stage_obs", _i32, _vp, _i32, C.POINTER(C.c_float), _i32)
+    _sig("cap_plan_run", _i32, _vp, _u64, _u32, _vp)
+    _sig("cap_plan_run_plain", _i32, _vp, _u64, _u32, _vp)
+    _sig("cap_plan_sync", _i32, _vp)
+    _sig("cap_plan_stats", _i32, _vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32))
+    _sig("cap_plan_tuning", _i32, _vp, C.POINTER(cap_plan_config))
+    EXPORTED += ["cap_plan_create", "cap_plan_destroy", "cap_plan_set_slot",
+                 "cap_plan_clear_slot", "cap_plan_stage_obs", "cap_plan_run",
+                 "cap_plan_run_plain", "cap_plan_sync", "cap_plan_stats", "cap_plan_tuning"]
+
+
+def _check(rc: int, what: str):
+    if rc != CAP_OK:
+        raise CapError(rc, what)
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor], dtype: torch.dtype, name: str, shape=None) -> Optional[int]:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+@dataclasses.dataclass
+class Model:
+    """Human model of Sec. III-A: K headings at speed v, step dt, beta grid, goals."""
+    K: int
+    speed: float
+    dt: float
+    beta: np.ndarray     # float32 [B]
+    goals: np.ndarray    # float32 [G, 2] metres
+
+    def __post_init__(self):
+        self.beta = np.ascontiguousarray(self.beta, np.float32).reshape(-1)
+        self.goals = np.ascontiguousarray(self.goals, np.float32).reshape(-1, 2)
+
+    @property
+    def B(self):
+        return int(self.beta.size)
+
+    @property
+    def G(self):
+        return int(self.goals.shape[0])
+
+    def c(self) -> cap_model:
+        return cap_model(self.K, float(self.speed), float(self.dt), self.B,
+                         self.beta.ctypes.data_as(C.POINTER(C.c_float)), self.G,
+                         self.goals.ctypes.data_as(C.POINTER(C.c_float)))
+
+
+def model_of(h) -> Model:
+    """Model of a scenes.Human."""
+    return Model(h.K, h.speed, h.dt, h.beta, h.goals)
+
+
+def grid_c(grid: Sequence) -> cap_grid:
+    x0, y0, cell, nx, ny = grid
+    return cap_grid(float(x0), float(y0), float(cell), int(nx), int(ny))
+
+
+def abi_version() -> int:
+    return _lib.cap_abi_version()
+
+
+def device_cu_count() -> int:
+    return _lib.cap_device_cu_count()
+
+
+# ----------------------------------------------------------------- belief
+def belief_reset(log_belief: torch.Tensor, stream=None):
+    G, B = log_belief.shape
+    _check(_lib.cap_belief_reset(G, B, _ptr(log_belief, torch.float64, "log_belief"),
+                                 _stream(stream)), "cap_belief_reset")
+    return log_belief
+
+
+def belief_update(model: Model, obs: torch.Tensor, log_belief: torch.Tensor,
+                  belief: Optional[torch.Tensor] = None, stream=None):
+    """Eq. (beta_update) over the transitions of obs [n+1, 2]; log_belief [G, B]
+    is updated in place; belief (optional) receives exp(log posterior)."""
+    m = model.c()
+    n_obs = obs.shape[0] - 1
+    _ptr(log_belief, torch.float64, "log_belief", (model.G, model.B))
+    _check(_lib.cap_belief_update(C.byref(m), _ptr(obs, torch.float32, "obs", (n_obs + 1, 2)),
+                                  n_obs, log_belief.data_ptr(),
+                                  _ptr(belief, torch.float64, "belief", (model.G, model.B)),
+                                  _stream(stream)), "cap_belief_update")
+    return log_belief, belief
+
+
+# ----------------------------------------------------------------- prediction
+def predict_occupancy(model: Model, grid: Sequence, z0: Sequence[float], belief: torch.Tensor,
+                      N: int, H: int, seed: int = 0, human_id: int = 0, cycle: int = 0,
+                      counts: Optional[torch.Tensor] = None,
+                      offgrid: Optional[torch.Tensor] = None, trace: bool = False, stream=None):
+    """Alg. 1 for one human.  Returns dict(counts [H,ny,nx] int32-view of uint32,
+    offgrid [H], trace_k [N,H] uint8, trace_pair [N] int32)."""
+    g = grid_c(grid)
+    dev = belief.device
+    if counts is None:
+        counts = torch.empty((H, g.ny, g.nx), dtype=torch.int32, device=dev)
+    if offgrid is None:
+        offgrid = torch.empty(H, dtype=torch.int32, device=dev)
+    tk = torch.empty((N, H), dtype=torch.uint8, device=dev) if trace else None
+    tp = torch.empty(N, dtype=torch.int32, device=dev) if trace else None
+    m = model.c()
+    z = (C.c_double * 2)(float(z0[0]), float(z0[1]))
+    _check(_lib.cap_predict_occupancy(
+        C.byref(m), C.byref(g), z, _ptr(belief, torch.float64, "belief", (model.G, model.B)),
+        N, H, seed, human_id, cycle, _ptr(counts, torch.int32, "counts", (H, g.ny, g.nx)),
+        _ptr(offgrid, torch.int32, "offgrid", (H,)), _ptr(tk, torch.uint8, "trace_k"),
+        _ptr(tp, torch.int32, "trace_pair"), _stream(stream)), "cap_predict_occupancy")
+    return {"counts": counts, "offgrid": offgrid, "trace_k": tk, "trace_pair": tp}
+
+
+def normalize(counts: torch.Tensor, N: int, probs: Optional[torch.Tensor] = None, stream=None):
+    """p = count / N (FP32)."""
+    if probs is None:
+        probs = torch.empty(counts.shape, dtype=torch.float32, device=counts.device)
+    _check(_lib.cap_normalize(_ptr(counts, torch.int32, "counts"), counts.numel(), N,
+                              _ptr(probs, torch.float32, "probs", tuple(counts.shape)),
+                              _stream(stream)), "cap_normalize")
+    return probs
+
+
+def philox_blocks(n: int, c0: int, c1: int, c2: int, c3: int, seed: int, device="cuda",
+                  stream=None) -> torch.Tensor:
+    """Raw Philox4x32-10 blocks for counters (c0+i, c1, c2, c3): int32 view [n, 4]."""
+    out = torch.empty((n, 4), dtype=torch.int32, device=device)
+    _check(_lib.cap_philox_blocks(n, c0, c1, c2, c3, seed, out.data_ptr(), _stream(stream)),
+           "cap_philox_blocks")
+    return out
+
+
+def simulate_tracks(K: int, speed: float, dt: float, frame: Sequence[float],
+                    start: torch.Tensor, beta: torch.Tensor, goal: torch.Tensor, T: int,
+                    seed: int = 0, stream_id: int = 0, stream=None):
+    """Synthetic humans.  start [n,2] f64, beta [n] f32, goal [n,2] f32 (device).
+    Returns (lattice [n,T+1,2] int32, positions [n,T+1,2] f32)."""
+    n = start.shape[0]
+    lat = torch.empty((n, T + 1, 2), dtype=torch.int32, device=start.device)
+    pos = torch.empty((n, T + 1, 2), dtype=torch.float32, device=start.device)
+    x0, y0, cell = frame
+    _check(_lib.cap_simulate_tracks(K, speed, dt, x0, y0, cell, n, T,
+                                    _ptr(start, torch.float64, "start", (n, 2)),
+                                    _ptr(beta, torch.float32, "beta", (n,)),
+                                    _ptr(goal, torch.float32, "goal", (n, 2)), seed, stream_id,
+                                    lat.data_ptr(), pos.data_ptr(), _stream(stream)),
+           "cap_simulate_tracks")
+    return lat, pos
+
+
+# ----------------------------------------------------------------- log-likelihood
+def _ll_args(K, speed, dt, tracks, lengths, goals, log_beta):
+    N, T1, _ = tracks.shape
+    G = goals.shape[0]
+    per_track = 1 if log_beta.dim() == 2 else 0
+    B = log_beta.shape[-1]
+    if per_track and log_beta.shape[0] != N:
+        raise ValueError("per-track log_beta must be [N, B]")
+    return (K, float(speed), float(dt), _ptr(tracks, torch.float32, "tracks"),
+            _ptr(lengths, torch.int32, "lengths", (N,)), N, T1 - 1,
+            _ptr(goals, torch.float32, "goals", (G, 2)), G,
+            _ptr(log_beta, torch.float32, "log_beta"), B, per_track)
+
+
+def loglik(K, speed, dt, tracks, lengths, goals, log_beta, stream=None) -> torch.Tensor:
+    """LL [N, B, G] FP64 (product form of Eq. beta_update over each track)."""
+    args = _ll_args(K, speed, dt, tracks, lengths, goals, log_beta)
+    N, G, B = args[5], args[8], args[10]
+    LL = torch.empty((N, B, G), dtype=torch.float64, device=tracks.device)
+    _check(_lib.cap_loglik(*args, LL.data_ptr(), _stream(stream)), "cap_loglik")
+    return LL
+
+
+def loglik_backward(K, speed, dt, tracks, lengths, goals, log_beta, dLL, stream=None):
+    """(dgoals [G,2] FP64, dlog_beta like log_beta in FP64)."""
+    args = _ll_args(K, speed, dt, tracks, lengths, goals, log_beta)
+    N, G, B, per_track = args[5], args[8], args[10], args[11]
+    dLL = dLL.to(torch.float64).contiguous()
+    _ptr(dLL, torch.float64, "dLL", (N, B, G))
+    dg = torch.empty((G, 2), dtype=torch.float64, device=tracks.device)
+    db = torch.empty(tuple(log_beta.shape), dtype=torch.float64, device=tracks.device)
+    ws_bytes = _lib.cap_loglik_backward_workspace(N, G, B, per_track)
+    ws = torch.empty(max(ws_bytes, 8), dtype=torch.uint8, device=tracks.device)
+    _check(_lib.cap_loglik_backward(*args, dLL.data_ptr(), dg.data_ptr(), db.data_ptr(),
+                                    ws.data_ptr(), ws_bytes, _stream(stream)),
+           "cap_loglik_backward")
+    return dg, db
+
+
+class LogLik(torch.autograd.Function):
+    """LL = LogLik.apply(goals [G,2] f32, log_beta [B] or [N,B] f32, tracks, lengths, K, speed, dt);
+    backward through the hand-written adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, goals, log_beta, tracks, lengths, K, speed, dt):
+        goals_c = goals.detach().contiguous()
+        lb_c = log_beta.detach().contiguous()
+        ctx.save_for_backward(goals_c, lb_c, tracks, lengths)
+        ctx.model = (K, speed, dt)
+        return loglik(K, speed, dt, tracks, lengths, goals_c, lb_c)
+
+    @staticmethod
+    def backward(ctx, dLL):
+        goals, lb, tracks, lengths = ctx.saved_tensors
+        K, speed, dt = ctx.model
+        dg, db = loglik_backward(K, speed, dt, tracks, lengths, goals, lb, dLL)
+        return dg.to(goals.dtype), db.to(lb.dtype), None, None, None, None, None

@@ -1,0 +1,141 @@
+// belief.hpp -- device side of the (beta, g) belief update, Eq. (beta_update)
+// in the log form of Sec. III-B, for one human per thread block.
+#pragma once
+
+#include "model.hpp"
+
+namespace capred {
+
+constexpr int kBeliefThreads = 256;
+constexpr int kBeliefChunk = 16;  // observed transitions staged in LDS at a time
+
+struct BeliefShared {
+  float ell[kBeliefChunk * CAP_MAX_J];
+  double red[kBeliefThreads / 64];
+};
+
+// Heading recovered from one observed transition: argmax_k <dz, (cos, sin)theta_k>
+// with the lowest k on ties; -1 when the displacement is below 1e-9 m.
+__device__ __forceinline__ int recover_heading(const BeliefModel& m, float dx, float dy) {
+  if (fmaf(dx, dx, dy * dy) < 1e-18f) return -1;
+  int ks = 0;
+  float best = -INFINITY;
+  for (int k = 0; k < m.K; ++k) {
+    const float v = fmaf(dx, m.cth[k], dy * m.sth[k]);
+    if (v > best) {
+      best = v;
+      ks = k;
+    }
+  }
+  return ks;
+}
+
+// log pi(k* | z; beta_b, g) for every b, FP32.  Delta_k = |a + s_k| - |a| with
+// a = z - g carried as an unevaluated sum (hi + lo, exact subtraction), from
+// the cancellation-free quotient (2 a.s_k + |s_k|^2) / (|a + s_k| + |a|); then
+// l_k = -beta Delta_k and log pi = l_{k*} - max l - log sum exp(l - max l).
+__device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, float zy, int ks,
+                                             float gx, float gy, const float* beta, int B,
+                                             float* out) {
+  if (ks < 0) {
+    for (int b = 0; b < B; ++b) out[b] = 0.f;
+    return;
+  }
+  const float ax = zx - gx, bx = ax - zx;
+  const float ax_lo = (zx - (ax - bx)) + (-gx - bx);
+  const float ay = zy - gy, by = ay - zy;
+  const float ay_lo = (zy - (ay - by)) + (-gy - by);
+  const float D2 = fmaf(ax, ax, ay * ay);
+  const float D = sqrtf(D2);
+  const float ax2 = ax + ax, ay2 = ay + ay;
+  float dl[CAP_MAX_K];
+  for (int k = 0; k < m.K; ++k) {
+    const float corr = fmaf(2.f * ax_lo, m.sx[k], fmaf(2.f * ay_lo, m.sy[k], m.s2[k]));
+    const float n = fmaf(ax2, m.sx[k], fmaf(ay2, m.sy[k], corr));
+    const float d = sqrtf(fmaxf(D2 + n, 0.f));
+    dl[k] = n / (d + D);
+  }
+  for (int b = 0; b < B; ++b) {
+    const float nbt = -beta[b];
+    float mx = -INFINITY;
+    for (int k = 0; k < m.K; ++k) mx = fmaxf(mx, nbt * dl[k]);
+    float s = 0.f;
+    for (int k = 0; k < m.K; ++k) s += expf(nbt * dl[k] - mx);
+    out[b] = (nbt * dl[ks] - mx) - logf(s);
+  }
+}
+
+__device__ __forceinline__ double block_reduce(double v, bool is_max, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double x = __shfl_xor(v, o, 64);
+    v = is_max ? fmax(v, x) : v + x;
+  }
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < nw; ++w) r = is_max ? fmax(r, red[w]) : r + red[w];
+  return r;
+}
+
+// One human's update: log_belief[j] += sum_t ell_t(j), renormalised by one
+// FP64 log-sum-exp.  All sums run in a fixed order (bitwise reproducible).
+__device__ void belief_update_block(const BeliefModel& m, const float* __restrict__ obs,
+                                    int n_obs, double* __restrict__ log_belief,
+                                    double* __restrict__ belief_out, BeliefShared& sh) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int G = m.G, B = m.B, J = G * B;
+  constexpr int kPerThread = CAP_MAX_J / kBeliefThreads;
+  double acc[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) acc[r] = 0.0;
+  float terms[CAP_MAX_B];
+  for (int t0 = 0; t0 < n_obs; t0 += kBeliefChunk) {
+    const int nt = min(kBeliefChunk, n_obs - t0);
+    for (int item = tid; item < nt * G; item += nthr) {
+      const int tl = item / G, g = item - tl * G, t = t0 + tl;
+      const float zx = obs[2 * t], zy = obs[2 * t + 1];
+      const int ks = recover_heading(m, obs[2 * t + 2] - zx, obs[2 * t + 3] - zy);
+      policy_terms(m, zx, zy, ks, m.gx[g], m.gy[g], m.beta, B, terms);
+      for (int b = 0; b < B; ++b) sh.ell[(tl * G + g) * B + b] = terms[b];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+      const int j = tid + r * nthr;
+      if (j < J)
+        for (int tl = 0; tl < nt; ++tl) acc[r] += (double)sh.ell[tl * J + j];
+    }
+    __syncthreads();
+  }
+  double v[kPerThread];
+  double mx = -INFINITY;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int j = tid + r * nthr;
+    v[r] = j < J ? log_belief[j] + acc[r] : -INFINITY;
+    mx = fmax(mx, v[r]);
+  }
+  mx = block_reduce(mx, true, sh.red);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int j = tid + r * nthr;
+    if (j < J) s += exp(v[r] - mx);
+  }
+  s = block_reduce(s, false, sh.red);
+  const double lse = mx + log(s);
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int j = tid + r * nthr;
+    if (j < J) {
+      const double lb = v[r] - lse;
+      log_belief[j] = lb;
+      if (belief_out) belief_out[j] = exp(lb);
+    }
+  }
+}
+
+}  // namespace capred

@@ -1,0 +1,253 @@
+// loglik.hip -- batched trajectory log-likelihood (product form of
+// Eq. beta_update over each track) and its adjoint with respect to the goal
+// positions and log beta.  One wavefront per (track, goal): lanes take
+// observed steps, FP32 policy terms are accumulated per lane in FP64 and
+// reduced across the wave by a fixed butterfly, so results are bitwise
+// reproducible.  The adjoint writes per-(track, goal) partials to the
+// workspace and a second kernel sums them in a fixed order (no atomics).
+#include "belief.hpp"
+
+namespace capred {
+
+constexpr int kLLThreads = 256;  // 4 wavefronts, each one (track, goal)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+struct LLArgs {
+  BeliefModel m;           // K, continuous steps and heading unit vectors
+  const float* tracks;     // [N][Tmax+1][2]
+  const int32_t* lengths;  // [N]
+  int32_t N, Tmax, G, B, per_track;
+  const float* goals;      // [G][2]
+  const float* log_beta;   // [B] or [N][B]
+};
+
+__device__ __forceinline__ void load_beta(const LLArgs& a, int n, float* beta) {
+  const float* lb = a.per_track ? a.log_beta + (size_t)n * a.B : a.log_beta;
+  for (int b = 0; b < a.B; ++b) beta[b] = expf(lb[b]);
+}
+
+__global__ void __launch_bounds__(kLLThreads) loglik_kernel(const LLArgs a, double* __restrict__ LL) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * (kLLThreads / 64) + (threadIdx.x >> 6);
+  if (item >= a.N * a.G) return;  // whole wavefront exits together
+  const int n = item / a.G, g = item - n * a.G;
+  const int len = a.lengths[n];
+  const float* z = a.tracks + (size_t)n * (a.Tmax + 1) * 2;
+  const float gx = a.goals[2 * g], gy = a.goals[2 * g + 1];
+  float beta[CAP_MAX_B], terms[CAP_MAX_B];
+  load_beta(a, n, beta);
+  double acc[CAP_MAX_B];
+  for (int b = 0; b < a.B; ++b) acc[b] = 0.0;
+  for (int t = lane; t < len; t += 64) {
+    const float zx = z[2 * t], zy = z[2 * t + 1];
+    const int ks = recover_heading(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
+    policy_terms(a.m, zx, zy, ks, gx, gy, beta, a.B, terms);
+    for (int b = 0; b < a.B; ++b) acc[b] += (double)terms[b];
+  }
+  for (int b = 0; b < a.B; ++b) {
+    const double s = wave_sum(acc[b]);
+    if (lane == 0) LL[((size_t)n * a.B + b) * a.G + g] = s;
+  }
+}
+
+// Per-step adjoint terms for one (z, goal) and every beta:
+//   d ell/d g        = -beta (E_p[yhat] - yhat_{k*}),
+//   d ell/d log beta = -beta (Delta_{k*} - E_p[Delta]),
+// with yhat_k = (a + s_k)/d_k and, to avoid cancellation between unit vectors,
+//   yhat_k - yhat_* = a (Delta_* - Delta_k)/(d_k d_*) + s_k/d_k - s_*/d_*.
+__global__ void __launch_bounds__(kLLThreads)
+    loglik_backward_kernel(const LLArgs a, const double* __restrict__ dLL,
+                           double* __restrict__ ws_g, double* __restrict__ ws_b) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * (kLLThreads / 64) + (threadIdx.x >> 6);
+  if (item >= a.N * a.G) return;
+  const int n = item / a.G, g = item - n * a.G;
+  const int len = a.lengths[n];
+  const int K = a.m.K, B = a.B;
+  const float* z = a.tracks + (size_t)n * (a.Tmax + 1) * 2;
+  const float gx = a.goals[2 * g], gy = a.goals[2 * g + 1];
+  float beta[CAP_MAX_B], w[CAP_MAX_B];
+  load_beta(a, n, beta);
+  for (int b = 0; b < B; ++b) w[b] = (float)dLL[((size_t)n * B + b) * a.G + g];
+  double agx = 0.0, agy = 0.0, ab[CAP_MAX_B];
+  for (int b = 0; b < B; ++b) ab[b] = 0.0;
+  float dl[CAP_MAX_K], dk[CAP_MAX_K];
+  for (int t = lane; t < len; t += 64) {
+    const float zx = z[2 * t], zy = z[2 * t + 1];
+    const int ks = recover_heading(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
+    if (ks < 0) continue;
+    const float ax = zx - gx, bx = ax - zx;
+    const float ax_lo = (zx - (ax - bx)) + (-gx - bx);
+    const float ay = zy - gy, by = ay - zy;
+    const float ay_lo = (zy - (ay - by)) + (-gy - by);
+    const float D2 = fmaf(ax, ax, ay * ay);
+    const float D = sqrtf(D2);
+    for (int k = 0; k < K; ++k) {
+      const float corr = fmaf(2.f * ax_lo, a.m.sx[k], fmaf(2.f * ay_lo, a.m.sy[k], a.m.s2[k]));
+      const float nk = fmaf(ax + ax, a.m.sx[k], fmaf(ay + ay, a.m.sy[k], corr));
+      dk[k] = sqrtf(fmaxf(D2 + nk, 0.f));
+      dl[k] = nk / (dk[k] + D);
+    }
+    const float ds = dk[ks];
+    for (int b = 0; b < B; ++b) {
+      const float nbt = -beta[b];
+      float mx = -INFINITY;
+      for (int k = 0; k < K; ++k) mx = fmaxf(mx, nbt * dl[k]);
+      float s = 0.f, ex = 0.f, ey = 0.f, ed = 0.f;
+      for (int k = 0; k < K; ++k) {
+        const float p = expf(nbt * dl[k] - mx);
+        s += p;
+        // yhat_k - yhat_*  (yhat := 0 where the distance is 0)
+        float ux, uy;
+        if (dk[k] > 0.f && ds > 0.f) {
+          const float v = (dl[ks] - dl[k]) / (dk[k] * ds);
+          ux = fmaf(ax, v, a.m.sx[k] / dk[k] - a.m.sx[ks] / ds);
+          uy = fmaf(ay, v, a.m.sy[k] / dk[k] - a.m.sy[ks] / ds);
+        } else if (dk[k] > 0.f) {
+          ux = (ax + a.m.sx[k]) / dk[k];
+          uy = (ay + a.m.sy[k]) / dk[k];
+        } else if (ds > 0.f) {
+          ux = -(ax + a.m.sx[ks]) / ds;
+          uy = -(ay + a.m.sy[ks]) / ds;
+        } else {
+          ux = 0.f;
+          uy = 0.f;
+        }
+        ex = fmaf(p, ux, ex);
+        ey = fmaf(p, uy, ey);
+        ed = fmaf(p, dl[k] - dl[ks], ed);
+      }
+      const float inv = 1.f / s;
+      // E[yhat] - yhat_* = ex/s ; E[Delta] - Delta_* = ed/s
+      agx += (double)(w[b] * (nbt * (ex * inv)));
+      agy += (double)(w[b] * (nbt * (ey * inv)));
+      ab[b] += (double)(w[b] * (beta[b] * (ed * inv)));
+    }
+  }
+  const double sgx = wave_sum(agx), sgy = wave_sum(agy);
+  if (lane == 0) {
+    ws_g[((size_t)n * a.G + g) * 2] = sgx;
+    ws_g[((size_t)n * a.G + g) * 2 + 1] = sgy;
+  }
+  for (int b = 0; b < B; ++b) {
+    const double s = wave_sum(ab[b]);
+    if (lane == 0) ws_b[((size_t)n * a.G + g) * B + b] = s;
+  }
+}
+
+// Fixed-order second stage: goals sum over tracks; log beta over (track, goal)
+// or, per track, over goals.
+__global__ void loglik_reduce_kernel(int N, int G, int B, int per_track,
+                                     const double* __restrict__ ws_g,
+                                     const double* __restrict__ ws_b, double* __restrict__ dgoals,
+                                     double* __restrict__ dlog_beta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 2 * G) {
+    const int g = i >> 1, c = i & 1;
+    double s = 0.0;
+    for (int n = 0; n < N; ++n) s += ws_g[((size_t)n * G + g) * 2 + c];
+    dgoals[i] = s;
+  }
+  const int nb = per_track ? N * B : B;
+  const int jb = i - 2 * G;
+  if (jb >= 0 && jb < nb) {
+    double s = 0.0;
+    if (per_track) {
+      const int n = jb / B, b = jb - n * B;
+      for (int g = 0; g < G; ++g) s += ws_b[((size_t)n * G + g) * B + b];
+    } else {
+      for (int n = 0; n < N; ++n)
+        for (int g = 0; g < G; ++g) s += ws_b[((size_t)n * G + g) * B + jb];
+    }
+    dlog_beta[jb] = s;
+  }
+}
+
+static cap_status make_ll_args(int32_t K, double speed, double dt, const float* tracks,
+                               const int32_t* lengths, int32_t N, int32_t Tmax,
+                               const float* goals, int32_t G, const float* log_beta, int32_t B,
+                               int32_t per_track, LLArgs* a) {
+  cap_status st = check_model_shape(K, speed, dt);
+  if (st != CAP_OK) return st;
+  if (N < 0 || Tmax < 0) return fail(CAP_E_INVALID, "N and Tmax must be >= 0");
+  if (G < 1 || G > CAP_MAX_G || B < 1 || B > CAP_MAX_B)
+    return fail(CAP_E_INVALID, "G in [1, 64] and B in [1, 16] required");
+  if (N > 0 && (!tracks || !lengths || !goals || !log_beta))
+    return fail(CAP_E_INVALID, "tracks/lengths/goals/log_beta is NULL");
+  a->m = make_belief_model(K, speed, dt, 0, nullptr, 0, nullptr);
+  a->tracks = tracks;
+  a->lengths = lengths;
+  a->N = N;
+  a->Tmax = Tmax;
+  a->G = G;
+  a->B = B;
+  a->per_track = per_track ? 1 : 0;
+  a->goals = goals;
+  a->log_beta = log_beta;
+  return CAP_OK;
+}
+
+}  // namespace capred
+
+using namespace capred;
+
+extern "C" cap_status cap_loglik(int32_t K, double speed, double dt, const float* tracks_dev,
+                                 const int32_t* lengths_dev, int32_t N, int32_t Tmax,
+                                 const float* goals_dev, int32_t G, const float* log_beta_dev,
+                                 int32_t B, int32_t per_track_beta, double* LL_dev, void* stream) {
+  LLArgs a;
+  cap_status st = make_ll_args(K, speed, dt, tracks_dev, lengths_dev, N, Tmax, goals_dev, G,
+                               log_beta_dev, B, per_track_beta, &a);
+  if (st != CAP_OK) return st;
+  if (N == 0) return CAP_OK;
+  if (!LL_dev) return fail(CAP_E_INVALID, "LL is NULL");
+  const int items = N * G, per_block = kLLThreads / 64;
+  hipLaunchKernelGGL(loglik_kernel, dim3((items + per_block - 1) / per_block), dim3(kLLThreads), 0,
+                     as_stream(stream), a, LL_dev);
+  CAP_HIP(hipGetLastError());
+  return CAP_OK;
+}
+
+extern "C" size_t cap_loglik_backward_workspace(int32_t N, int32_t G, int32_t B,
+                                                int32_t per_track_beta) {
+  (void)per_track_beta;
+  if (N < 0 || G < 0 || B < 0) return 0;
+  return (size_t)N * G * (2 + B) * sizeof(double);
+}
+
+extern "C" cap_status cap_loglik_backward(int32_t K, double speed, double dt,
+                                          const float* tracks_dev, const int32_t* lengths_dev,
+                                          int32_t N, int32_t Tmax, const float* goals_dev,
+                                          int32_t G, const float* log_beta_dev, int32_t B,
+                                          int32_t per_track_beta, const double* dLL_dev,
+                                          double* dgoals_dev, double* dlog_beta_dev, void* ws_dev,
+                                          size_t ws_bytes, void* stream) {
+  LLArgs a;
+  cap_status st = make_ll_args(K, speed, dt, tracks_dev, lengths_dev, N, Tmax, goals_dev, G,
+                               log_beta_dev, B, per_track_beta, &a);
+  if (st != CAP_OK) return st;
+  if (!dgoals_dev || !dlog_beta_dev) return fail(CAP_E_INVALID, "dgoals/dlog_beta is NULL");
+  if (N > 0 && !dLL_dev) return fail(CAP_E_INVALID, "dLL is NULL");
+  const size_t need = cap_loglik_backward_workspace(N, G, B, per_track_beta);
+  if (need > 0 && (!ws_dev || ws_bytes < need))
+    return fail(CAP_E_WORKSPACE, "workspace smaller than cap_loglik_backward_workspace()");
+  hipStream_t s = as_stream(stream);
+  double* ws_g = static_cast<double*>(ws_dev);
+  double* ws_b = ws_g + (size_t)N * G * 2;
+  if (N > 0) {
+    const int items = N * G, per_block = kLLThreads / 64;
+    hipLaunchKernelGGL(loglik_backward_kernel, dim3((items + per_block - 1) / per_block),
+                       dim3(kLLThreads), 0, s, a, dLL_dev, ws_g, ws_b);
+    CAP_HIP(hipGetLastError());
+  }
+  const int outs = 2 * G + (per_track_beta ? N * B : B);
+  hipLaunchKernelGGL(loglik_reduce_kernel, dim3((outs + 255) / 256), dim3(256), 0, s, N, G, B,
+                     a.per_track, ws_g, ws_b, dgoals_dev, dlog_beta_dev);
+  CAP_HIP(hipGetLastError());
+  return CAP_OK;
+}

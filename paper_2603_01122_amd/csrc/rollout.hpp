@@ -1,0 +1,196 @@
+// rollout.hpp -- device side of Alg. 1 for one tile of particles of one human:
+// (beta, g) draw from the belief, H Boltzmann-heading lattice steps held in
+// registers, and per-step emplacement through an LDS-privatised histogram
+// window flushed to the global uint32 grid with coalesced atomics.
+#pragma once
+
+#include "common.hpp"
+
+namespace capred {
+
+// Everything the rollout needs about one human (trivially copyable; passed by
+// value to the single-human kernel and stored in device memory for batches).
+struct RolloutDesc {
+  int32_t N, H, K, B, G, nx, ny;
+  int32_t X0, Y0;           // start on the lattice (grid frame)
+  int32_t Rx, Ry;           // max |S_kx|, |S_ky|: reach per step, lattice units
+  uint32_t human, cycle;
+  int32_t shift;            // 1: subtract the largest exponent (large beta * step)
+  HeadingTable T;           // lattice-unit steps and squared lengths (FP32)
+  int32_t Sx[CAP_MAX_K], Sy[CAP_MAX_K];
+  float nbeta[CAP_MAX_B];   // -beta * q * log2(e)
+  int32_t GX[CAP_MAX_G], GY[CAP_MAX_G];
+  const double* belief;     // [G][B]
+  uint32_t* counts;         // [H][ny][nx]
+  uint32_t* offgrid;        // [H] or null
+  uint8_t* trace_k;         // [N][H] or null
+  int32_t* trace_pair;      // [N] or null
+};
+
+struct TileShared {
+  double P[CAP_MAX_J];      // pair CDF (sequential FP64 prefix sums)
+  int2 S[CAP_MAX_K];        // lattice steps for the dynamic heading index
+  int2 goal[CAP_MAX_G];
+  float nbeta[CAP_MAX_B];
+  uint32_t off[2];          // off-grid counters of the two in-flight steps
+  int last_pos;
+};
+
+__device__ __forceinline__ int64_t floor_shift16(int64_t v) { return v >> kLatticeShift; }
+
+// Histogram window of step t: every particle is within t * (Rx, Ry) lattice
+// units of the start, so its cell lies in [floor((X0 - tRx)/2^16),
+// floor((X0 + tRx)/2^16)] (clipped to the grid).  Uniform across the block.
+struct Window {
+  int x0, y0, w, h;
+};
+
+__device__ __forceinline__ Window step_window(const RolloutDesc& d, int t) {
+  Window win;
+  const int64_t rx = (int64_t)t * d.Rx, ry = (int64_t)t * d.Ry;
+  int64_t lx = floor_shift16((int64_t)d.X0 - rx), hx = floor_shift16((int64_t)d.X0 + rx);
+  int64_t ly = floor_shift16((int64_t)d.Y0 - ry), hy = floor_shift16((int64_t)d.Y0 + ry);
+  lx = lx < 0 ? 0 : lx;
+  ly = ly < 0 ? 0 : ly;
+  hx = hx > d.nx - 1 ? d.nx - 1 : hx;
+  hy = hy > d.ny - 1 ? d.ny - 1 : hy;
+  win.x0 = (int)lx;
+  win.y0 = (int)ly;
+  win.w = hx >= lx ? (int)(hx - lx + 1) : 0;
+  win.h = hy >= ly ? (int)(hy - ly + 1) : 0;
+  return win;
+}
+
+__device__ __forceinline__ uint32_t pick_word(const uint4& w, int s) {
+  return s == 0 ? w.x : (s == 1 ? w.y : (s == 2 ? w.z : w.w));
+}
+
+// Processes particles [first, first + P * blockDim.x) of human d (clipped to N).
+// win: 2 * cap words of LDS, zero on entry and on exit.
+template <int KT, int P>
+__device__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_lo,
+                             uint32_t seed_hi, TileShared& sh, uint32_t* win, int cap) {
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int J = d.G * d.B;
+  // ---- shared tables
+  if (tid == 0) {
+    double acc = 0.0;
+    int last = 0;
+    for (int j = 0; j < J; ++j) {
+      const double b = d.belief[j];
+      acc += b;
+      sh.P[j] = acc;
+      if (b > 0.0) last = j;
+    }
+    sh.last_pos = last;
+    sh.off[0] = 0u;
+    sh.off[1] = 0u;
+  }
+  for (int k = tid; k < d.K; k += nthr) sh.S[k] = make_int2(d.Sx[k], d.Sy[k]);
+  for (int g = tid; g < d.G; g += nthr) sh.goal[g] = make_int2(d.GX[g], d.GY[g]);
+  for (int b = tid; b < d.B; b += nthr) sh.nbeta[b] = d.nbeta[b];
+  __syncthreads();
+
+  // ---- per-particle (beta, g) draw, held for the whole horizon
+  const uint32_t c3_pair = 2u * d.cycle, c3_head = 2u * d.cycle + 1u;
+  int64_t idx[P];
+  bool act[P];
+  int32_t X[P], Y[P], GXp[P], GYp[P];
+  float nb[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    idx[p] = first + (int64_t)p * nthr + tid;
+    act[p] = idx[p] < d.N;
+    X[p] = d.X0;
+    Y[p] = d.Y0;
+    GXp[p] = 0;
+    GYp[p] = 0;
+    nb[p] = 0.f;
+    if (act[p]) {
+      const uint4 w = philox10((uint32_t)idx[p], 0u, d.human, c3_pair, seed_lo, seed_hi);
+      const double u = uniform24d(w.x);
+      int lo = 0, hi = J;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sh.P[mid] > u) hi = mid;
+        else lo = mid + 1;
+      }
+      const int j = lo < J ? lo : sh.last_pos;
+      const int g = j / d.B, b = j - g * d.B;
+      GXp[p] = sh.goal[g].x;
+      GYp[p] = sh.goal[g].y;
+      nb[p] = sh.nbeta[b];
+      if (d.trace_pair) d.trace_pair[idx[p]] = j;
+    }
+  }
+
+  const bool shift = d.shift != 0;
+  const size_t plane = (size_t)d.nx * (size_t)d.ny;
+  uint4 rw[P];
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  for (int t = 1; t <= d.H; ++t) {
+    const int s = (t - 1) & 3;
+    if (s == 0) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        rw[p] = philox10((uint32_t)idx[p], (uint32_t)((t - 1) >> 2), d.human, c3_head, seed_lo,
+                         seed_hi);
+    }
+    const Window wd = step_window(d, t);
+    const bool lds_mode = wd.w * wd.h <= cap;
+    uint32_t* buf = win + (t & 1) * cap;
+    uint32_t* grid_t = d.counts + (size_t)(t - 1) * plane;
+    bool off_any = false;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      bool off = false;
+      if (act[p]) {
+        const float u = uniform24f(pick_word(rw[p], s));
+        const int k = draw_heading<KT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), nb[p], u,
+                                       shift, d.T, d.K);
+        const int2 st = sh.S[k];
+        X[p] += st.x;
+        Y[p] += st.y;
+        if (d.trace_k) d.trace_k[(size_t)idx[p] * d.H + (t - 1)] = (uint8_t)k;
+        const int cx = X[p] >> kLatticeShift, cy = Y[p] >> kLatticeShift;
+        if ((unsigned)cx < (unsigned)d.nx && (unsigned)cy < (unsigned)d.ny) {
+          const unsigned lx = (unsigned)(cx - wd.x0), ly = (unsigned)(cy - wd.y0);
+          if (lds_mode && lx < (unsigned)wd.w && ly < (unsigned)wd.h)
+            atomicAdd(buf + ly * wd.w + lx, 1u);
+          else
+            atomicAdd(grid_t + (size_t)cy * d.nx + cx, 1u);
+        } else {
+          off = true;
+        }
+      }
+      off_any |= off;
+      const uint64_t m = __ballot(off);
+      if (m && lane == 0) atomicAdd(&sh.off[t & 1], (uint32_t)__popcll(m));
+    }
+    (void)off_any;
+    __syncthreads();
+    // ---- flush the window of step t (coalesced along rows), clear it
+    if (lds_mode) {
+      for (int r = wave; r < wd.h; r += nwaves) {
+        uint32_t* row = buf + r * wd.w;
+        uint32_t* grow = grid_t + (size_t)(wd.y0 + r) * d.nx + wd.x0;
+        for (int c = lane; c < wd.w; c += 64) {
+          const uint32_t v = row[c];
+          if (v) {
+            atomicAdd(grow + c, v);
+            row[c] = 0u;
+          }
+        }
+      }
+    }
+    if (tid == 0) {
+      const uint32_t v = sh.off[t & 1];
+      if (v && d.offgrid) atomicAdd(d.offgrid + (t - 1), v);
+      sh.off[t & 1] = 0u;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace capred
