@@ -1,0 +1,280 @@
+#!/usr/bin/env python
+"""Benchmark of the serving cycle on the 16-human workload.
+
+Workload: 16 humans with particle counts log-uniform in [2^14, 2^18]
+(about 1.42e6 particles), 2-6 goals each, 9 beta values, 16 headings at
+1.2 m/s, dt = 0.02 s, H = 100 steps, one 256x256 grid (0.05 m) per human.
+One step = one serving cycle over all humans: a new observed position per
+human, belief update, grid clear, one persistent batched rollout launch
+(hipGraph), normalisation.  Synthetic data: humans are simulated on the GPU
+by the library's Boltzmann-policy track simulator; all inputs are resident
+before the timed region (only the per-cycle observation/descriptor copy,
+about 16 x 3 KB, crosses PCIe, as it would in serving).
+
+Reported: particle-steps/s of back-to-back batched cycles (`value`); the
+same for the plain per-human sequential launches (the paper's multi-human
+procedure, Sec. IV-B) and their ratio; p50/p99 latency of a 125 Hz paced
+loop; the rollout kernel's roofline (live HIP-event timing); and the FP64
+oracle timed on the host cores on one full cycle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # full-rate VALU lane operations per second (MI355X)
+METRIC = "particle-steps/sec + p99 cycle latency, 16 humans @125Hz, batched vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_ops(K: int, r: dict) -> float:
+    """Minimal VALU work per particle-step of the stable-form rollout, in
+    full-rate lane-operation equivalents (rates r from the probes):
+      per heading: 2 FMA (2a.s_k + |s_k|^2), add (D^2 + n), add (d + D),
+                   2 mul (quotient, beta scale), add (prefix), compare+count
+                   = 9 full-rate, plus sqrt, reciprocal, exp2;
+      per step:    offset/convert/|a|^2/2a/uniform/threshold/step/cell/bounds
+                   = 22 full-rate plus one sqrt (|a|);
+      Philox:      one 10-round block per 4 steps = 5 wide multiplies and
+                   10 full-rate ops per step."""
+    return (K * (9 + r["sqrt"] + r["rcp"] + r["exp2"]) + 22 + r["sqrt"] + 10 + 5 * r["mul64"])
+
+
+def measure_rates(capred, torch) -> dict:
+    """Issue cost of each op kind relative to an FP32 FMA, from the probes."""
+    cus = capred.device_cu_count()
+    blocks = cus * 8
+    sink = torch.zeros(blocks, dtype=torch.float32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    iters = 4096
+    for kind in ("fma", "exp2", "sqrt", "rcp", "mul64"):
+        capred.probe(kind, 64, blocks, sink)
+        e0.record()
+        capred.probe(kind, iters, blocks, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        ops = blocks * 256 * 8 * iters
+        out[kind] = ops / (ms * 1e-3)
+    rates = {k: out["fma"] / v for k, v in out.items()}
+    rates["fma_lane_ops_per_s"] = out["fma"]
+    return rates
+
+
+def simulate(capred, torch, np, humans, T):
+    start = torch.tensor(np.array([h.start for h in humans]), dtype=torch.float64, device="cuda")
+    beta = torch.tensor(np.array([h.true_beta for h in humans], np.float32), device="cuda")
+    goal = torch.tensor(np.array([h.goals[h.true_goal] for h in humans], np.float32),
+                        device="cuda")
+    h0 = humans[0]
+    _, pos = capred.simulate_tracks(h0.K, h0.speed, h0.dt, h0.frame, start, beta, goal, T,
+                                    seed=0, stream_id=0)
+    pos = pos.cpu().numpy()
+    return {h.hid: pos[i] for i, h in enumerate(humans)}
+
+
+def make_server(capred, humans, tuning, tracks):
+    from paper_2603_01122_amd.serve import HumanRequest, Server
+    h0 = humans[0]
+    srv = Server(h0.K, h0.speed, h0.dt, len(humans), max(h.H for h in humans),
+                 max(h.grid[3] for h in humans), max(h.grid[4] for h in humans),
+                 max(h.G for h in humans), max(h.B for h in humans), tuning=tuning)
+    for h in humans:
+        srv.submit(HumanRequest(h.hid, capred.model_of(h), h.grid, h.N, h.H, tracks[h.hid][0]))
+    return srv
+
+
+def cpu_baseline(scene, tracks_np, max_seconds):
+    """The FP64 oracle on one full serving cycle (belief update + Alg. 1 for all
+    humans), on every host core this process may use."""
+    import oracle
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    steps = 0
+    done = 0
+    for h in scene.humans:
+        obs = tracks_np[h.hid][:2]
+        _, b, _ = oracle.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals,
+                                       obs=obs)
+        oracle.predict(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals, grid=h.grid,
+                       z0=tuple(obs[-1].astype(float)), belief=b, N=h.N, H=h.H, seed=0,
+                       human=h.hid, cycle=0, nthreads=threads)
+        steps += h.N * h.H
+        done += 1
+        if time.perf_counter() - t0 > max_seconds:
+            break
+    dt = time.perf_counter() - t0
+    sample = (f"one full serving cycle of the 16-human workload ({done} humans, "
+              f"{steps} particle-steps)" if done == len(scene.humans) else
+              f"{done} of {len(scene.humans)} humans of one cycle ({steps} particle-steps)")
+    return {"value": steps / dt, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed batched cycles")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--plain-steps", type=int, default=30)
+    ap.add_argument("--paced-cycles", type=int, default=10000)
+    ap.add_argument("--rate", type=float, default=125.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no "
+              "multi-GPU path; humans would be sharded across GPUs with no exchange step.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2603_01122_amd import capred, scenes, tune
+    from paper_2603_01122_amd.serve import run_paced
+
+    scene = scenes.config3()
+    humans = scene.humans
+    psteps = scene.particle_steps
+    n_tune = 2 * 9 * 10
+    T = args.warmup + args.steps + args.plain_steps + args.paced_cycles + n_tune + 64
+    log(f"simulating {len(humans)} tracks x {T} steps")
+    tracks = simulate(capred, torch, np, humans, T)
+
+    rates = measure_rates(capred, torch)
+    log(f"probe rates (cost relative to FMA): { {k: round(v, 3) for k, v in rates.items() if k != 'fma_lane_ops_per_s'} }")
+
+    if args.no_tune:
+        best, table, best_plain, table_plain = {}, {}, {}, {}
+    else:
+        best, table = tune.autotune(humans, tracks, use_cache=False)
+        best_plain, table_plain = tune.autotune(humans, tracks, plain=True, use_cache=False,
+                                                cycles=3)
+    log(f"tuned batched: {best}  plain: {best_plain}")
+
+    # ---------------------------------------------------------- batched, back-to-back
+    srv = make_server(capred, humans, best, tracks)
+    c = 0
+    for _ in range(args.warmup):
+        srv.step({h.hid: tracks[h.hid][c + 1] for h in humans})
+        c += 1
+    srv.drain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        srv.step({h.hid: tracks[h.hid][c + 1] for h in humans})
+        c += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    srv.drain()
+    sec_per_cycle = (t1 - t0) / args.steps
+    value = psteps / sec_per_cycle
+    log(f"batched: {1e3 * sec_per_cycle:.3f} ms/cycle, {value:.3e} particle-steps/s")
+
+    # ---------------------------------------------------------- rollout kernel alone
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    e1.record(stream)
+    durs = []
+    for _ in range(20):
+        srv.plan.replay_rollout(stream, e0, e1)
+        torch.cuda.synchronize()
+        durs.append(e0.elapsed_time(e1) * 1e-3)
+    roll = float(np.mean(durs))
+    W = algorithmic_ops(humans[0].K, rates)
+    achieved = W * psteps / roll
+    roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
+                "kernel": "plan_rollout_kernel", "ms_per_launch": round(roll * 1e3, 4),
+                "ops_per_particle_step": round(W, 2),
+                "particle_steps_per_launch": psteps,
+                "rates_vs_fma": {k: round(v, 3) for k, v in rates.items()
+                                 if k != "fma_lane_ops_per_s"},
+                "fma_lane_ops_per_s": float(f"{rates['fma_lane_ops_per_s']:.4e}")}
+    log(f"rollout kernel {roll * 1e3:.3f} ms, {W:.1f} ops/particle-step, frac {achieved / PEAK_LANE_OPS:.3f}")
+
+    # ---------------------------------------------------------- paced 125 Hz serving
+    base = c
+    lat = None
+    if args.paced_cycles > 0:
+        log(f"paced loop: {args.paced_cycles} cycles at {args.rate} Hz")
+        lat = run_paced(srv, lambda k: {h.hid: tracks[h.hid][base + k + 1] for h in humans},
+                        args.paced_cycles, args.rate,
+                        progress=(2000, lambda k: log(f"  paced {k} cycles")))
+        c += args.paced_cycles
+    srv.close()
+
+    # ---------------------------------------------------------- plain per-human launches
+    psrv = make_server(capred, humans, best_plain, tracks)
+    for k in range(3):
+        psrv.step({h.hid: tracks[h.hid][k + 1] for h in humans}, plain=True)
+    psrv.drain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(3, 3 + args.plain_steps):
+        psrv.step({h.hid: tracks[h.hid][k + 1] for h in humans}, plain=True)
+    torch.cuda.synchronize()
+    plain_sec = (time.perf_counter() - t0) / args.plain_steps
+    psrv.close()
+    plain_value = psteps / plain_sec
+    log(f"plain: {1e3 * plain_sec:.3f} ms/cycle, {plain_value:.3e} particle-steps/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one full cycle)")
+        cpu = cpu_baseline(scene, tracks, args.cpu_seconds)
+
+    latency = None
+    if lat is not None:
+        period = 1.0 / args.rate
+        latency = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                   "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+                   "max_ms": round(float(lat.max()) * 1e3, 4),
+                   "cycles": int(lat.size), "rate_hz": args.rate,
+                   "deadline_ms": round(period * 1e3, 3),
+                   "deadline_misses": int(np.count_nonzero(lat > period))}
+    result = {
+        "metric": METRIC,
+        "value": float(f"{value:.6e}"),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec_per_cycle * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "16 humans, N log-uniform [2^14, 2^18] (sum %d), 2-6 goals, 9 beta, "
+                               "K=16, v=1.2 m/s, dt=0.02 s, H=100, 256x256 grids at 0.05 m"
+                               % sum(h.N for h in humans),
+                   "particle_steps_per_cycle": psteps, "humans": len(humans),
+                   "tuning": best, "plain_tuning": best_plain},
+        "latency": latency,
+        "plain": {"value": float(f"{plain_value:.6e}"), "ms_per_step": round(plain_sec * 1e3, 4),
+                  "batched_over_plain": round(value / plain_value, 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "context": "paper: ~125 Hz for one human, n=8192, T=10, |U|=96 on an RTX 2080 Ti "
+                   "(Tab. 1, JAX/XLA), about 1.0e7 particle-steps/s; different workload and hardware",
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

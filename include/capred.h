@@ -245,6 +245,11 @@ cap_status cap_plan_stage_obs(cap_plan* plan, int32_t slot, const float* xy, int
  * Every active slot is predicted from its newest observed position.  The
  * staging area is reusable when this returns.  cycle < 2^31 - 1. */
 cap_status cap_plan_run(cap_plan* plan, uint64_t seed, uint32_t cycle, void* stream);
+/* Re-launch the rollout of the most recent cycle alone (grid clear, then the
+ * persistent rollout kernel), recording ev_start / ev_end (hipEvent_t, may be
+ * NULL) on `stream` immediately around the rollout launch.  The outputs are
+ * recomputed identically (same keys).  Used to time the rollout kernel. */
+cap_status cap_plan_replay_rollout(cap_plan* plan, void* stream, void* ev_start, void* ev_end);
 /* Block the host until the last run has completed on the device. */
 cap_status cap_plan_sync(cap_plan* plan);
 /* Totals over the active slots: particles, particle-steps, rollout tiles. */
@@ -259,6 +264,17 @@ cap_status cap_plan_tuning(const cap_plan* plan, cap_plan_config* out);
  * on `stream`.  Same kernels' arithmetic and random keys as cap_plan_run, so
  * the outputs are identical; used to measure the batched form against it. */
 cap_status cap_plan_run_plain(cap_plan* plan, uint64_t seed, uint32_t cycle, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Measurement probes for the roofline of the rollout (not part of the method):
+ * cap_probe runs `blocks` x 256 threads, each issuing 8 independent chains of
+ * `iters` operations of one kind: 0 FP32 FMA, 1 exp2, 2 sqrt, 3 reciprocal,
+ * 4 32x32->64-bit multiply (the Philox round product), 5 LDS atomic add.
+ * Time it with events on `stream`; sink_dev is a [blocks] FP32 buffer that is
+ * written only to keep the chains alive.  cap_copy is a plain device copy of
+ * `bytes` (16-byte aligned), used to calibrate hardware byte counters. */
+cap_status cap_probe(int32_t kind, int64_t iters, int32_t blocks, float* sink_dev, void* stream);
+cap_status cap_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -93,7 +93,7 @@ def lib():
             L.orc_tie_check.argtypes = [
                 i32, d, d, i32, _f32p, i32, _f32p, d, d, d, d, d, _f64p,
                 i64, i32, u64, u32, u32, _nullable(_i64p), i64,
-                _i32p, _u8p, d, _i32p, _i32p, i32]
+                _i32p, _u8p, d, d, _i32p, _i32p, i32]
             L.orc_tie_check.restype = i32
             L.orc_recover_controls.argtypes = [i32, _f32p, i32, _i32p, _nullable(_f64p)]
             L.orc_recover_controls.restype = i32
@@ -175,10 +175,11 @@ def predict(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed=0, human=
     return {"counts": cnt, "offgrid": off, "trace_k": tk, "trace_pair": tp, "trace_cell": tc}
 
 
-def tie_check(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed, human, cycle,
-              other_pair, other_k, window=1e-6, idx=None, nthreads=None):
+def tie_check(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed=0, human=0, cycle=0,
+              other_pair, other_k, window=1e-6, pair_window=0.0, idx=None, nthreads=None):
     """Replay particles and classify another implementation's choices:
-    status 0 identical, 1 first difference at a CDF tie within `window`, 2 unexplained."""
+    status 0 identical, 1 first difference at a heading-CDF tie within `window`
+    (or a pair-CDF tie within `pair_window`), 2 unexplained."""
     x0, y0, cell, nx, ny = grid
     beta = np.ascontiguousarray(beta, np.float32)
     goals = np.ascontiguousarray(goals, np.float32).reshape(-1)
@@ -191,7 +192,8 @@ def tie_check(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed, human,
                              float(z0[0]), float(z0[1]), belief, N, H, seed, human, cycle,
                              idx_arr, 0 if idx_arr is None else idx_arr.size,
                              np.ascontiguousarray(other_pair, np.int32),
-                             np.ascontiguousarray(other_k, np.uint8).reshape(-1), window, st, first,
+                             np.ascontiguousarray(other_k, np.uint8).reshape(-1), window,
+                             pair_window, st, first,
                              nthreads or default_threads())
     _check(rc, "tie_check")
     return st, first

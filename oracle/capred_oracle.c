@@ -281,7 +281,7 @@ int orc_tie_check(int K, double speed, double dt,
                   int64_t N, int H, uint64_t seed, uint32_t human, uint32_t cycle,
                   const int64_t* idx, int64_t n_idx,
                   const int32_t* other_pair, const uint8_t* other_k, double window,
-                  int32_t* status, int32_t* first, int nthreads) {
+                  double pair_window, int32_t* status, int32_t* first, int nthreads) {
   int32_t Sx[ORC_MAXK], Sy[ORC_MAXK];
   if (orc_lattice_steps(K, speed, dt, cell, Sx, Sy)) return -1;
   const double q = orc_pitch(cell);
@@ -316,8 +316,8 @@ int orc_tie_check(int K, double speed, double dt,
       int ok = 0;
       if (jo >= 0 && jo < J) {
         /* other chose a later pair: all of P[j..jo-1] must sit within window of u */
-        if (jo > j) ok = (P[jo - 1] - up) <= window;
-        else ok = (up - P[jo]) <= window;
+        if (jo > j) ok = (P[jo - 1] - up) <= pair_window;
+        else ok = (up - P[jo]) <= pair_window;
       }
       status[r] = ok ? 1 : 2;
       continue;

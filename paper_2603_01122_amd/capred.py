@@ -90,7 +90,9 @@ _sig("cap_loglik_backward", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32,
      _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("cap_loglik_backward_workspace", _sz, _i32, _i32, _i32, _i32)
 _sig("cap_philox_blocks", _i32, _i64, _u32, _u32, _u32, _u32, _u64, _vp, _vp)
-EXPORTED = ["cap_philox_blocks", "cap_abi_version", "cap_last_error", "cap_device_cu_count", "cap_belief_update",
+_sig("cap_probe", _i32, _i32, _i64, _i32, _vp, _vp)
+_sig("cap_copy", _i32, _vp, _vp, _sz, _vp)
+EXPORTED = ["cap_probe", "cap_copy", "cap_philox_blocks", "cap_abi_version", "cap_last_error", "cap_device_cu_count", "cap_belief_update",
             "cap_belief_reset", "cap_predict_occupancy", "cap_normalize", "cap_simulate_tracks",
             "cap_loglik", "cap_loglik_backward", "cap_loglik_backward_workspace"]
 if hasattr(_lib, "cap_plan_create"):
@@ -104,7 +106,8 @@ if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_sync", _i32, _vp)
     _sig("cap_plan_stats", _i32, _vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32))
     _sig("cap_plan_tuning", _i32, _vp, C.POINTER(cap_plan_config))
-    EXPORTED += ["cap_plan_create", "cap_plan_destroy", "cap_plan_set_slot",
+    _sig("cap_plan_replay_rollout", _i32, _vp, _vp, _vp, _vp)
+    EXPORTED += ["cap_plan_replay_rollout", "cap_plan_create", "cap_plan_destroy", "cap_plan_set_slot",
                  "cap_plan_clear_slot", "cap_plan_stage_obs", "cap_plan_run",
                  "cap_plan_run_plain", "cap_plan_sync", "cap_plan_stats", "cap_plan_tuning"]
 
@@ -246,6 +249,20 @@ def philox_blocks(n: int, c0: int, c1: int, c2: int, c3: int, seed: int, device=
     return out
 
 
+PROBE_KINDS = {"fma": 0, "exp2": 1, "sqrt": 2, "rcp": 3, "mul64": 4, "lds_atomic": 5}
+
+
+def probe(kind: str, iters: int, blocks: int, sink: torch.Tensor, stream=None):
+    """Launches one throughput probe (8 chains x iters ops per thread, 256 threads/block)."""
+    _check(_lib.cap_probe(PROBE_KINDS[kind], iters, blocks, _ptr(sink, torch.float32, "sink"),
+                          _stream(stream)), "cap_probe")
+
+
+def copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    _check(_lib.cap_copy(src.data_ptr(), dst.data_ptr(), src.numel() * src.element_size(),
+                         _stream(stream)), "cap_copy")
+
+
 def simulate_tracks(K: int, speed: float, dt: float, frame: Sequence[float],
                     start: torch.Tensor, beta: torch.Tensor, goal: torch.Tensor, T: int,
                     seed: int = 0, stream_id: int = 0, stream=None):
@@ -321,3 +338,109 @@ class LogLik(torch.autograd.Function):
         K, speed, dt = ctx.model
         dg, db = loglik_backward(K, speed, dt, tracks, lengths, goals, lb, dLL)
         return dg.to(goals.dtype), db.to(lb.dtype), None, None, None, None, None
+
+
+# ----------------------------------------------------------------- batched plans
+@dataclasses.dataclass
+class SlotBuffers:
+    """Device buffers of one admitted human (ring of per-cycle outputs)."""
+    counts: torch.Tensor      # [ring, H, ny, nx] int32 (uint32 counts)
+    probs: Optional[torch.Tensor]   # [ring, H, ny, nx] f32
+    offgrid: torch.Tensor     # [ring, H] int32
+    log_belief: torch.Tensor  # [G, B] f64 state
+    belief: torch.Tensor      # [ring, G, B] f64 posterior
+
+    @staticmethod
+    def allocate(model: Model, grid, H: int, ring: int, probs: bool = True, device="cuda"):
+        nx, ny = int(grid[3]), int(grid[4])
+        return SlotBuffers(
+            torch.empty((ring, H, ny, nx), dtype=torch.int32, device=device),
+            torch.empty((ring, H, ny, nx), dtype=torch.float32, device=device) if probs else None,
+            torch.empty((ring, H), dtype=torch.int32, device=device),
+            torch.empty((model.G, model.B), dtype=torch.float64, device=device),
+            torch.empty((ring, model.G, model.B), dtype=torch.float64, device=device))
+
+
+class Plan:
+    """Batched many-human prediction (cap_plan_*): one persistent rollout launch
+    per cycle, captured in hipGraphs, with continuous admission of humans."""
+
+    def __init__(self, K: int, speed: float, dt: float, n_slots: int, max_obs: int = 1,
+                 ring: int = 2, block_threads: int = 0, particles_per_thread: int = 0,
+                 lds_bytes: int = 0, grid_blocks: int = 0):
+        cfg = cap_plan_config(n_slots, K, speed, dt, max_obs, ring, block_threads,
+                              particles_per_thread, lds_bytes, grid_blocks)
+        h = C.c_void_p()
+        _check(_lib.cap_plan_create(C.byref(cfg), C.byref(h)), "cap_plan_create")
+        self._h = h
+        self.K, self.speed, self.dt, self.ring = K, speed, dt, ring
+        self.n_slots = n_slots
+        self.buffers = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.cap_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tuning(self) -> dict:
+        c = cap_plan_config()
+        _check(_lib.cap_plan_tuning(self._h, C.byref(c)), "cap_plan_tuning")
+        return {f: getattr(c, f) for f, _ in cap_plan_config._fields_}
+
+    def admit(self, slot: int, human_id: int, model: Model, grid, N: int, H: int,
+              last_xy, buffers: SlotBuffers, reset_belief: bool = True):
+        if model.K != self.K:
+            raise ValueError("model K differs from the plan's")
+        desc = cap_slot_desc()
+        desc.human_id = human_id
+        desc.N, desc.H, desc.B, desc.G = N, H, model.B, model.G
+        desc.beta = model.beta.ctypes.data_as(C.POINTER(C.c_float))
+        desc.goals = model.goals.ctypes.data_as(C.POINTER(C.c_float))
+        desc.grid = grid_c(grid)
+        desc.last_xy[0], desc.last_xy[1] = float(last_xy[0]), float(last_xy[1])
+        desc.counts_dev = _ptr(buffers.counts, torch.int32, "counts",
+                               (self.ring, H, int(grid[4]), int(grid[3])))
+        desc.offgrid_dev = _ptr(buffers.offgrid, torch.int32, "offgrid", (self.ring, H))
+        desc.probs_dev = _ptr(buffers.probs, torch.float32, "probs")
+        desc.log_belief_dev = _ptr(buffers.log_belief, torch.float64, "log_belief",
+                                   (model.G, model.B))
+        desc.belief_dev = _ptr(buffers.belief, torch.float64, "belief",
+                               (self.ring, model.G, model.B))
+        desc.reset_belief = 1 if reset_belief else 0
+        _check(_lib.cap_plan_set_slot(self._h, slot, C.byref(desc)), "cap_plan_set_slot")
+        self.buffers[slot] = buffers
+
+    def retire(self, slot: int):
+        _check(_lib.cap_plan_clear_slot(self._h, slot), "cap_plan_clear_slot")
+        self.buffers.pop(slot, None)
+
+    def stage(self, slot: int, xy):
+        a = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
+        _check(_lib.cap_plan_stage_obs(self._h, slot, a.ctypes.data_as(C.POINTER(C.c_float)),
+                                       a.shape[0]), "cap_plan_stage_obs")
+
+    def run(self, seed: int, cycle: int, stream=None):
+        _check(_lib.cap_plan_run(self._h, seed, cycle, _stream(stream)), "cap_plan_run")
+
+    def run_plain(self, seed: int, cycle: int, stream=None):
+        _check(_lib.cap_plan_run_plain(self._h, seed, cycle, _stream(stream)),
+               "cap_plan_run_plain")
+
+    def replay_rollout(self, stream=None, ev_start=None, ev_end=None):
+        _check(_lib.cap_plan_replay_rollout(
+            self._h, _stream(stream), None if ev_start is None else ev_start.cuda_event,
+            None if ev_end is None else ev_end.cuda_event), "cap_plan_replay_rollout")
+
+    def sync(self):
+        _check(_lib.cap_plan_sync(self._h), "cap_plan_sync")
+
+    def stats(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(_lib.cap_plan_stats(self._h, C.byref(a), C.byref(b), C.byref(c)), "cap_plan_stats")
+        return a.value, b.value, c.value

@@ -1,0 +1,630 @@
+// plan.hip -- batched many-human prediction: one persistent rollout launch per
+// cycle for every active human, captured with the belief update, the grid
+// clear and the normalisation in hipGraphs (one pair per ring entry), with
+// per-cycle descriptors refreshed by a single host-to-device copy.
+//
+// Scheduling: the tiles of all humans (P * blockDim particles each) form one
+// index space split into 8 contiguous ranges, one per XCD; block b starts on
+// the range of XCD (b mod 8) -- workgroups are dispatched round-robin over the
+// XCDs -- so that the tiles of one human share that XCD's L2, and steals from
+// the other ranges when its own is exhausted.  Every cycle's results depend
+// only on (human id, cycle, seed), never on the slot or the tile order:
+// histogram updates are integer atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "belief.hpp"
+
+namespace capred {
+
+constexpr int kMaxObs = 8;
+constexpr int kXcds = 8;
+
+struct SlotDev {
+  RolloutDesc rd;          // rollout of this cycle (start, ring-entry outputs)
+  BeliefModel bm;          // continuous model for the update
+  double* log_belief;      // belief state [G][B]
+  float* probs;            // ring-entry probabilities or null
+  int64_t n_cells;         // H * nx * ny
+  int32_t n_obs;           // new transitions this cycle
+  int32_t reset;           // write the uniform prior before updating
+  float obs[(kMaxObs + 1) * 2];
+};
+
+struct CycleHeader {
+  uint32_t seed_lo, seed_hi, cycle;
+  int32_t n_active, n_tiles, per_tile;
+  int32_t tile_begin[CAP_MAX_SLOTS + 1];
+};
+
+__device__ __forceinline__ const SlotDev* slots_of(const uint8_t* base) {
+  return reinterpret_cast<const SlotDev*>(base + sizeof(CycleHeader));
+}
+
+// ---------------------------------------------------------------- kernels
+__global__ void __launch_bounds__(kBeliefThreads)
+    plan_update_kernel(const uint8_t* __restrict__ base, int only) {
+  __shared__ BeliefShared sh;
+  const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
+  const int s = only >= 0 ? only : (int)blockIdx.x;
+  if (s >= H->n_active) return;
+  const SlotDev& sd = slots_of(base)[s];
+  const int J = sd.bm.G * sd.bm.B;
+  if (sd.reset) {
+    for (int j = threadIdx.x; j < J; j += blockDim.x) sd.log_belief[j] = -log((double)J);
+    __syncthreads();
+  }
+  belief_update_block(sd.bm, sd.obs, sd.n_obs, sd.log_belief, const_cast<double*>(sd.rd.belief),
+                      sh);
+}
+
+// Clears the counts (and off-grid counters) of every active slot -- or of one
+// -- and resets the tile queues for the rollout that follows.
+__global__ void __launch_bounds__(256)
+    plan_zero_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int only) {
+  const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) queues[threadIdx.x] = 0u;
+  const SlotDev* sl = slots_of(base);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s0 = only >= 0 ? only : 0, s1 = only >= 0 ? only + 1 : H->n_active;
+  for (int s = s0; s < s1 && s < H->n_active; ++s) {
+    uint32_t* p = sl[s].rd.counts;
+    const size_t n = (size_t)sl[s].n_cells;
+    uint4* p4 = reinterpret_cast<uint4*>(p);
+    const size_t n4 = (reinterpret_cast<uintptr_t>(p) & 15u) ? 0 : n / 4;
+    for (size_t v = i0; v < n4; v += stride) p4[v] = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t v = n4 * 4 + i0; v < n; v += stride) p[v] = 0u;
+    if (sl[s].rd.offgrid)
+      for (size_t v = i0; v < (size_t)sl[s].rd.H; v += stride) sl[s].rd.offgrid[v] = 0u;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    plan_normalize_kernel(const uint8_t* __restrict__ base, int only) {
+  const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
+  const SlotDev* sl = slots_of(base);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s0 = only >= 0 ? only : 0, s1 = only >= 0 ? only + 1 : H->n_active;
+  for (int s = s0; s < s1 && s < H->n_active; ++s) {
+    float* p = sl[s].probs;
+    if (!p) continue;
+    const uint32_t* c = sl[s].rd.counts;
+    const float N = (float)sl[s].rd.N;
+    const size_t n = (size_t)sl[s].n_cells;
+    const bool al = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(p)) & 15u) == 0;
+    const size_t n4 = al ? n / 4 : 0;
+    const uint4* c4 = reinterpret_cast<const uint4*>(c);
+    float4* p4 = reinterpret_cast<float4*>(p);
+    for (size_t v = i0; v < n4; v += stride) {
+      const uint4 x = c4[v];
+      p4[v] = make_float4((float)x.x / N, (float)x.y / N, (float)x.z / N, (float)x.w / N);
+    }
+    for (size_t v = n4 * 4 + i0; v < n; v += stride) p[v] = (float)c[v] / N;
+  }
+}
+
+__device__ __forceinline__ int slot_of_tile(const CycleHeader* H, int tile) {
+  int lo = 0, hi = H->n_active;  // largest s with tile_begin[s] <= tile
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (H->tile_begin[mid] <= tile) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int KT, int P>
+__global__ void __launch_bounds__(1024)
+    plan_rollout_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int cap) {
+  __shared__ TileShared sh;
+  __shared__ int s_tile;
+  extern __shared__ uint32_t win[];
+  const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
+  const SlotDev* sl = slots_of(base);
+  for (int i = threadIdx.x; i < 2 * cap; i += blockDim.x) win[i] = 0u;
+  const int n_tiles = H->n_tiles;
+  const int home = blockIdx.x % kXcds;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int t = -1;
+      for (int k = 0; k < kXcds && t < 0; ++k) {
+        const int q = (home + k) % kXcds;
+        const int lo = (int)(((int64_t)n_tiles * q) / kXcds);
+        const int hi = (int)(((int64_t)n_tiles * (q + 1)) / kXcds);
+        if (lo >= hi) continue;
+        const uint32_t got = atomicAdd(queues + q, 1u);
+        if ((int64_t)lo + got < hi) t = lo + (int)got;
+      }
+      s_tile = t;
+    }
+    __syncthreads();
+    const int tile = __builtin_amdgcn_readfirstlane(s_tile);
+    if (tile < 0) break;
+    const int s = __builtin_amdgcn_readfirstlane(slot_of_tile(H, tile));
+    const int64_t first = (int64_t)(tile - H->tile_begin[s]) * H->per_tile;
+    // rollout_tile starts and ends with a barrier: s_tile is not rewritten
+    // before every thread has read it.
+    rollout_tile<KT, P>(sl[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap);
+  }
+}
+
+// One human's tiles, one block per tile (the per-human reference launch).
+template <int KT, int P>
+__global__ void __launch_bounds__(1024)
+    plan_rollout_one_kernel(const uint8_t* __restrict__ base, int s, int cap) {
+  __shared__ TileShared sh;
+  extern __shared__ uint32_t win[];
+  const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
+  for (int i = threadIdx.x; i < 2 * cap; i += blockDim.x) win[i] = 0u;
+  const int64_t first = (int64_t)blockIdx.x * H->per_tile;
+  rollout_tile<KT, P>(slots_of(base)[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap);
+}
+
+// ---------------------------------------------------------------- host
+struct HostSlot {
+  bool active = false;
+  SlotDev tmpl;            // static part (rollout/belief model, buffers)
+  cap_grid grid;
+  uint32_t* counts = nullptr;
+  uint32_t* offgrid = nullptr;
+  float* probs = nullptr;
+  double* belief = nullptr;
+  int64_t n_cells = 0;
+  float last[2] = {0.f, 0.f};
+  int n_staged = 0;
+  float staged[kMaxObs * 2];
+  bool reset = false;
+};
+
+struct Entry {
+  uint32_t* queues = nullptr;   // this entry's 8 tile counters (device)
+  uint8_t* dev = nullptr;       // header + slots
+  uint8_t* host = nullptr;      // pinned mirror
+  hipGraphExec_t upd = nullptr, main = nullptr;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+typedef void (*RolloutFn)(const uint8_t*, uint32_t*, int);
+typedef void (*RolloutOneFn)(const uint8_t*, int, int);
+
+}  // namespace capred
+
+struct cap_plan {
+  cap_plan_config cfg;
+  std::vector<capred::HostSlot> slots;
+  std::vector<capred::Entry> ring;
+  uint32_t* queues = nullptr;   // ring * 8 tile counters (device)
+  size_t entry_bytes = 0;
+  int cap_words = 0;            // LDS window words per buffer
+  int grid_blocks = 0;
+  int per_tile = 0;
+  const void* rollout_fn = nullptr;
+  const void* rollout_one_fn = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_update = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool have_last = false;
+  int64_t last_run_entry = -1;
+  // last staged totals
+  int64_t particles = 0, psteps = 0;
+  int32_t tiles = 0;
+};
+
+namespace capred {
+
+template <int KT>
+static void pick_fns(int P, const void** r, const void** one) {
+  switch (P) {
+    case 1: *r = (const void*)plan_rollout_kernel<KT, 1>; *one = (const void*)plan_rollout_one_kernel<KT, 1>; break;
+    case 2: *r = (const void*)plan_rollout_kernel<KT, 2>; *one = (const void*)plan_rollout_one_kernel<KT, 2>; break;
+    default: *r = (const void*)plan_rollout_kernel<KT, 4>; *one = (const void*)plan_rollout_one_kernel<KT, 4>; break;
+  }
+}
+
+static void select_kernels(int K, int P, const void** r, const void** one) {
+  switch (K) {
+    case 4: pick_fns<4>(P, r, one); break;
+    case 8: pick_fns<8>(P, r, one); break;
+    case 16: pick_fns<16>(P, r, one); break;
+    case 32: pick_fns<32>(P, r, one); break;
+    default: pick_fns<0>(P, r, one); break;
+  }
+}
+
+static size_t header_bytes(int n_active) {
+  return sizeof(CycleHeader) + (size_t)n_active * sizeof(SlotDev);
+}
+
+static cap_status launch_rollout(cap_plan* p, const Entry& e, hipStream_t s) {
+  const uint8_t* base = e.dev;
+  uint32_t* q = e.queues;
+  void* args[] = {(void*)&base, (void*)&q, (void*)&p->cap_words};
+  CAP_HIP(hipLaunchKernel(p->rollout_fn, dim3(p->grid_blocks), dim3(p->cfg.block_threads), args,
+                          (size_t)2 * p->cap_words * sizeof(uint32_t), s));
+  return CAP_OK;
+}
+
+static cap_status record_graphs(cap_plan* p, Entry& e) {
+  hipStream_t s = p->cap_stream;
+  hipGraph_t g = nullptr;
+  const int minus1 = -1;
+  // belief update of every active slot
+  CAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(plan_update_kernel, dim3(p->cfg.n_slots), dim3(kBeliefThreads), 0, s,
+                     (const uint8_t*)e.dev, minus1);
+  CAP_HIP(hipStreamEndCapture(s, &g));
+  CAP_HIP(hipGraphInstantiate(&e.upd, g, nullptr, nullptr, 0));
+  CAP_HIP(hipGraphDestroy(g));
+  // clear -> persistent rollout -> normalise
+  CAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(plan_zero_kernel, dim3(2048), dim3(256), 0, s, (const uint8_t*)e.dev,
+                     e.queues, minus1);
+  cap_status st = launch_rollout(p, e, s);
+  hipLaunchKernelGGL(plan_normalize_kernel, dim3(4096), dim3(256), 0, s, (const uint8_t*)e.dev,
+                     minus1);
+  hipError_t err = hipStreamEndCapture(s, &g);
+  if (st != CAP_OK) return st;
+  if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
+  CAP_HIP(hipGraphInstantiate(&e.main, g, nullptr, nullptr, 0));
+  CAP_HIP(hipGraphDestroy(g));
+  return CAP_OK;
+}
+
+static void destroy_plan(cap_plan* p) {
+  if (!p) return;
+  for (auto& e : p->ring) {
+    if (e.upd) (void)hipGraphExecDestroy(e.upd);
+    if (e.main) (void)hipGraphExecDestroy(e.main);
+    if (e.done) (void)hipEventDestroy(e.done);
+    if (e.dev) (void)hipFree(e.dev);
+    if (e.host) (void)hipHostFree(e.host);
+  }
+  if (p->queues) (void)hipFree(p->queues);
+  if (p->ev_update) (void)hipEventDestroy(p->ev_update);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  delete p;
+}
+
+// Fills ring entry e's host mirror from the active slots; returns its size.
+static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
+  uint8_t* hostp = p->ring[e].host;
+  CycleHeader* H = reinterpret_cast<CycleHeader*>(hostp);
+  SlotDev* out = reinterpret_cast<SlotDev*>(hostp + sizeof(CycleHeader));
+  H->seed_lo = (uint32_t)seed;
+  H->seed_hi = (uint32_t)(seed >> 32);
+  H->cycle = cycle;
+  H->per_tile = p->per_tile;
+  int n = 0, tiles = 0;
+  int64_t parts = 0, steps = 0;
+  for (auto& hs : p->slots) {
+    if (!hs.active) continue;
+    SlotDev& sd = out[n];
+    std::memcpy(&sd, &hs.tmpl, sizeof(SlotDev));
+    const int R = p->cfg.ring;
+    const int re = (int)(cycle % (uint32_t)R);
+    sd.rd.cycle = cycle;
+    sd.rd.counts = hs.counts + (size_t)re * hs.n_cells;
+    sd.rd.offgrid = hs.offgrid ? hs.offgrid + (size_t)re * sd.rd.H : nullptr;
+    sd.probs = hs.probs ? hs.probs + (size_t)re * hs.n_cells : nullptr;
+    sd.rd.belief = hs.belief + (size_t)re * sd.bm.G * sd.bm.B;
+    sd.n_cells = hs.n_cells;
+    sd.reset = hs.reset ? 1 : 0;
+    hs.reset = false;
+    sd.n_obs = hs.n_staged;
+    sd.obs[0] = hs.last[0];
+    sd.obs[1] = hs.last[1];
+    for (int i = 0; i < 2 * hs.n_staged; ++i) sd.obs[2 + i] = hs.staged[i];
+    if (hs.n_staged > 0) {
+      hs.last[0] = hs.staged[2 * hs.n_staged - 2];
+      hs.last[1] = hs.staged[2 * hs.n_staged - 1];
+    }
+    hs.n_staged = 0;
+    // the rollout starts from the newest observed position (validated at staging)
+    sd.rd.X0 = (int32_t)lattice_coord((double)hs.last[0], hs.grid.x0, hs.grid.cell);
+    sd.rd.Y0 = (int32_t)lattice_coord((double)hs.last[1], hs.grid.y0, hs.grid.cell);
+    H->tile_begin[n] = tiles;
+    tiles += (int)((sd.rd.N + p->per_tile - 1) / p->per_tile);
+    parts += sd.rd.N;
+    steps += (int64_t)sd.rd.N * sd.rd.H;
+    ++n;
+  }
+  H->tile_begin[n] = tiles;
+  H->n_active = n;
+  H->n_tiles = tiles;
+  p->particles = parts;
+  p->psteps = steps;
+  p->tiles = tiles;
+  return header_bytes(n);
+}
+
+static cap_status wait_entry(cap_plan* p, int e) {
+  Entry& en = p->ring[e];
+  if (en.pending) {
+    CAP_HIP(hipEventSynchronize(en.done));
+    en.pending = false;
+  }
+  return CAP_OK;
+}
+
+static cap_status check_position(const HostSlot& hs, float x, float y, int H, int32_t reach) {
+  if (!std::isfinite(x) || !std::isfinite(y)) return fail(CAP_E_INVALID, "position is not finite");
+  const double X = lattice_coord((double)x, hs.grid.x0, hs.grid.cell);
+  const double Y = lattice_coord((double)y, hs.grid.y0, hs.grid.cell);
+  const double r = (double)H * (double)reach;
+  if (std::fabs(X) + r > 2.1e9 || std::fabs(Y) + r > 2.1e9)
+    return fail(CAP_E_INVALID, "position + H steps leave the int32 lattice of the grid");
+  return CAP_OK;
+}
+
+}  // namespace capred
+
+using namespace capred;
+
+extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** out) {
+  if (!cfg_in || !out) return fail(CAP_E_INVALID, "config or out is NULL");
+  *out = nullptr;
+  cap_plan_config cfg = *cfg_in;
+  cap_status st = check_model_shape(cfg.K, cfg.speed, cfg.dt);
+  if (st != CAP_OK) return st;
+  if (cfg.n_slots < 1 || cfg.n_slots > CAP_MAX_SLOTS) return fail(CAP_E_INVALID, "n_slots out of range");
+  if (cfg.max_obs < 1 || cfg.max_obs > kMaxObs) return fail(CAP_E_INVALID, "max_obs must be in [1, 8]");
+  if (cfg.ring == 0) cfg.ring = 2;
+  if (cfg.ring < 1 || cfg.ring > 4) return fail(CAP_E_INVALID, "ring must be in [1, 4]");
+  if (cfg.block_threads == 0) cfg.block_threads = 1024;
+  if (cfg.block_threads != 256 && cfg.block_threads != 512 && cfg.block_threads != 1024)
+    return fail(CAP_E_INVALID, "block_threads must be 256, 512 or 1024");
+  if (cfg.particles_per_thread == 0) cfg.particles_per_thread = 1;
+  if (cfg.particles_per_thread != 1 && cfg.particles_per_thread != 2 &&
+      cfg.particles_per_thread != 4)
+    return fail(CAP_E_INVALID, "particles_per_thread must be 1, 2 or 4");
+  if (cfg.lds_bytes == 0) cfg.lds_bytes = 75 * 1024;
+  if (cfg.lds_bytes < 2048 || cfg.lds_bytes > 144 * 1024)
+    return fail(CAP_E_INVALID, "lds_bytes must be in [2 KiB, 144 KiB]");
+  cap_plan* p = new cap_plan();
+  p->cfg = cfg;
+  p->slots.resize(cfg.n_slots);
+  p->ring.resize(cfg.ring);
+  p->per_tile = cfg.block_threads * cfg.particles_per_thread;
+  p->cap_words = cfg.lds_bytes / (2 * (int)sizeof(uint32_t));
+  select_kernels(cfg.K, cfg.particles_per_thread, &p->rollout_fn, &p->rollout_one_fn);
+  const size_t dyn = (size_t)2 * p->cap_words * sizeof(uint32_t);
+  hipError_t e = hipFuncSetAttribute(p->rollout_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)dyn);
+  (void)e;  // not required on gfx950; the occupancy query below validates the size
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p->rollout_fn, cfg.block_threads, dyn);
+  if (e != hipSuccess || per_cu < 1) {
+    destroy_plan(p);
+    return e != hipSuccess ? hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor")
+                           : fail(CAP_E_INVALID, "LDS window too large for one block per CU");
+  }
+  const int cus = cap_device_cu_count();
+  if (cfg.grid_blocks == 0) cfg.grid_blocks = std::max(1, cus) * per_cu;
+  p->cfg.grid_blocks = cfg.grid_blocks;
+  p->grid_blocks = cfg.grid_blocks;
+  p->entry_bytes = header_bytes(cfg.n_slots);
+  hipError_t he;
+#define CAP_TRY(call)                       \
+  do {                                      \
+    he = (call);                            \
+    if (he != hipSuccess) {                 \
+      destroy_plan(p);                      \
+      return hip_fail(he, #call);           \
+    }                                       \
+  } while (0)
+  CAP_TRY(hipMalloc(&p->queues, (size_t)cfg.ring * kXcds * sizeof(uint32_t)));
+  CAP_TRY(hipMemset(p->queues, 0, (size_t)cfg.ring * kXcds * sizeof(uint32_t)));
+  for (int e = 0; e < cfg.ring; ++e) p->ring[e].queues = p->queues + (size_t)e * kXcds;
+  CAP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  CAP_TRY(hipEventCreateWithFlags(&p->ev_update, hipEventDisableTiming));
+  for (auto& en : p->ring) {
+    CAP_TRY(hipMalloc(&en.dev, p->entry_bytes));
+    CAP_TRY(hipMemset(en.dev, 0, p->entry_bytes));
+    CAP_TRY(hipHostMalloc(&en.host, p->entry_bytes, hipHostMallocDefault));
+    std::memset(en.host, 0, p->entry_bytes);
+    CAP_TRY(hipEventCreateWithFlags(&en.done, hipEventDisableTiming));
+  }
+  CAP_TRY(hipDeviceSynchronize());
+#undef CAP_TRY
+  for (auto& en : p->ring) {
+    st = record_graphs(p, en);
+    if (st != CAP_OK) {
+      destroy_plan(p);
+      return st;
+    }
+  }
+  *out = p;
+  return CAP_OK;
+}
+
+extern "C" void cap_plan_destroy(cap_plan* plan) {
+  if (!plan) return;
+  for (int e = 0; e < (int)plan->ring.size(); ++e) (void)wait_entry(plan, e);
+  destroy_plan(plan);
+}
+
+extern "C" cap_status cap_plan_set_slot(cap_plan* p, int32_t slot, const cap_slot_desc* d) {
+  if (!p || !d) return fail(CAP_E_INVALID, "plan or desc is NULL");
+  if (slot < 0 || slot >= p->cfg.n_slots) return fail(CAP_E_INVALID, "slot out of range");
+  HostSlot& hs = p->slots[slot];
+  if (hs.active) return fail(CAP_E_CAPACITY, "slot is occupied");
+  cap_model m{p->cfg.K, p->cfg.speed, p->cfg.dt, d->B, d->beta, d->G, d->goals};
+  cap_status st = check_model(&m);
+  if (st != CAP_OK) return st;
+  if ((st = check_grid(&d->grid)) != CAP_OK) return st;
+  if (!d->counts_dev || !d->log_belief_dev || !d->belief_dev)
+    return fail(CAP_E_INVALID, "counts, log_belief and belief buffers are required");
+  HostSlot ns;
+  std::memset(&ns.tmpl, 0, sizeof(SlotDev));
+  st = make_rollout_desc(m.K, m.speed, m.dt, m.B, m.beta, m.G, m.goals, d->grid, d->N, d->H,
+                         &ns.tmpl.rd);
+  if (st != CAP_OK) return st;
+  ns.grid = d->grid;
+  if ((st = check_position(ns, d->last_xy[0], d->last_xy[1], d->H,
+                           std::max(ns.tmpl.rd.Rx, ns.tmpl.rd.Ry))) != CAP_OK)
+    return st;
+  ns.tmpl.rd.human = d->human_id;
+  ns.tmpl.bm = make_belief_model(m.K, m.speed, m.dt, m.B, m.beta, m.G, m.goals);
+  ns.tmpl.log_belief = d->log_belief_dev;
+  ns.counts = d->counts_dev;
+  ns.offgrid = d->offgrid_dev;
+  ns.probs = d->probs_dev;
+  ns.belief = d->belief_dev;
+  ns.n_cells = (int64_t)d->H * d->grid.nx * d->grid.ny;
+  ns.last[0] = d->last_xy[0];
+  ns.last[1] = d->last_xy[1];
+  ns.reset = d->reset_belief != 0;
+  ns.active = true;
+  hs = ns;
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_clear_slot(cap_plan* p, int32_t slot) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  if (slot < 0 || slot >= p->cfg.n_slots) return fail(CAP_E_INVALID, "slot out of range");
+  p->slots[slot].active = false;
+  p->slots[slot].n_staged = 0;
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_stage_obs(cap_plan* p, int32_t slot, const float* xy,
+                                         int32_t n_new) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  if (slot < 0 || slot >= p->cfg.n_slots || !p->slots[slot].active)
+    return fail(CAP_E_INVALID, "slot is not active");
+  HostSlot& hs = p->slots[slot];
+  if (n_new < 0 || hs.n_staged + n_new > p->cfg.max_obs)
+    return fail(CAP_E_CAPACITY, "more staged observations than max_obs");
+  if (n_new > 0 && !xy) return fail(CAP_E_INVALID, "xy is NULL");
+  const int32_t reach = std::max(hs.tmpl.rd.Rx, hs.tmpl.rd.Ry);
+  for (int i = 0; i < n_new; ++i) {
+    cap_status st = check_position(hs, xy[2 * i], xy[2 * i + 1], hs.tmpl.rd.H, reach);
+    if (st != CAP_OK) return st;
+  }
+  for (int i = 0; i < 2 * n_new; ++i) hs.staged[2 * hs.n_staged + i] = xy[i];
+  hs.n_staged += n_new;
+  return CAP_OK;
+}
+
+static cap_status begin_cycle(cap_plan* p, uint64_t seed, uint32_t cycle, hipStream_t s,
+                              int* e_out, size_t* bytes) {
+  if (cycle >= 0x7FFFFFFFu) return fail(CAP_E_INVALID, "cycle must be < 2^31 - 1");
+  const int e = (int)(cycle % (uint32_t)p->cfg.ring);
+  cap_status st = wait_entry(p, e);
+  if (st != CAP_OK) return st;
+  *bytes = build_entry(p, e, seed, cycle);
+  CAP_HIP(hipMemcpyAsync(p->ring[e].dev, p->ring[e].host, *bytes, hipMemcpyHostToDevice, s));
+  if (p->have_last && p->last_stream != s) CAP_HIP(hipStreamWaitEvent(s, p->ev_update, 0));
+  *e_out = e;
+  p->last_run_entry = e;
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_run(cap_plan* p, uint64_t seed, uint32_t cycle, void* stream) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  hipStream_t s = as_stream(stream);
+  int e = 0;
+  size_t bytes = 0;
+  cap_status st = begin_cycle(p, seed, cycle, s, &e, &bytes);
+  if (st != CAP_OK) return st;
+  Entry& en = p->ring[e];
+  CAP_HIP(hipGraphLaunch(en.upd, s));
+  CAP_HIP(hipEventRecord(p->ev_update, s));
+  CAP_HIP(hipGraphLaunch(en.main, s));
+  CAP_HIP(hipEventRecord(en.done, s));
+  en.pending = true;
+  p->last_stream = s;
+  p->have_last = true;
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_run_plain(cap_plan* p, uint64_t seed, uint32_t cycle,
+                                         void* stream) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  hipStream_t s = as_stream(stream);
+  int e = 0;
+  size_t bytes = 0;
+  cap_status st = begin_cycle(p, seed, cycle, s, &e, &bytes);
+  if (st != CAP_OK) return st;
+  Entry& en = p->ring[e];
+  const CycleHeader* H = reinterpret_cast<const CycleHeader*>(en.host);
+  const SlotDev* sl = reinterpret_cast<const SlotDev*>(en.host + sizeof(CycleHeader));
+  const uint8_t* base = en.dev;
+  for (int i = 0; i < H->n_active; ++i) {
+    hipLaunchKernelGGL(plan_update_kernel, dim3(1), dim3(kBeliefThreads), 0, s, base, i);
+    if (i == H->n_active - 1) CAP_HIP(hipEventRecord(p->ev_update, s));
+    const size_t n = (size_t)sl[i].n_cells;
+    const unsigned zb = (unsigned)std::min<size_t>((n / 4 + 255) / 256 + 1, 2048);
+    hipLaunchKernelGGL(plan_zero_kernel, dim3(zb), dim3(256), 0, s, base, en.queues, i);
+    const int tiles = H->tile_begin[i + 1] - H->tile_begin[i];
+    int si = i;
+    void* args[] = {(void*)&base, (void*)&si, (void*)&p->cap_words};
+    CAP_HIP(hipLaunchKernel(p->rollout_one_fn, dim3(tiles), dim3(p->cfg.block_threads), args,
+                            (size_t)2 * p->cap_words * sizeof(uint32_t), s));
+    if (sl[i].probs) {
+      const unsigned nb = (unsigned)std::min<size_t>((n / 4 + 255) / 256 + 1, 4096);
+      hipLaunchKernelGGL(plan_normalize_kernel, dim3(nb), dim3(256), 0, s, base, i);
+    }
+  }
+  if (H->n_active == 0) CAP_HIP(hipEventRecord(p->ev_update, s));
+  CAP_HIP(hipGetLastError());
+  CAP_HIP(hipEventRecord(en.done, s));
+  en.pending = true;
+  p->last_stream = s;
+  p->have_last = true;
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_replay_rollout(cap_plan* p, void* stream, void* ev_start,
+                                              void* ev_end) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  if (p->last_run_entry < 0) return fail(CAP_E_INVALID, "no cycle has run on this plan");
+  hipStream_t s = as_stream(stream);
+  const Entry& en = p->ring[p->last_run_entry];
+  const int minus1 = -1;
+  hipLaunchKernelGGL(plan_zero_kernel, dim3(2048), dim3(256), 0, s, (const uint8_t*)en.dev,
+                     en.queues, minus1);
+  if (ev_start) CAP_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(ev_start), s));
+  cap_status st = launch_rollout(p, en, s);
+  if (st != CAP_OK) return st;
+  if (ev_end) CAP_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(ev_end), s));
+  CAP_HIP(hipGetLastError());
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_sync(cap_plan* p) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  for (int e = 0; e < (int)p->ring.size(); ++e) {
+    cap_status st = wait_entry(p, e);
+    if (st != CAP_OK) return st;
+  }
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_stats(const cap_plan* p, int64_t* particles,
+                                     int64_t* particle_steps, int32_t* tiles) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  int64_t parts = 0, steps = 0;
+  int32_t t = 0;
+  for (const auto& hs : p->slots) {
+    if (!hs.active) continue;
+    parts += hs.tmpl.rd.N;
+    steps += (int64_t)hs.tmpl.rd.N * hs.tmpl.rd.H;
+    t += (int32_t)((hs.tmpl.rd.N + p->per_tile - 1) / p->per_tile);
+  }
+  if (particles) *particles = parts;
+  if (particle_steps) *particle_steps = steps;
+  if (tiles) *tiles = t;
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_tuning(const cap_plan* p, cap_plan_config* out) {
+  if (!p || !out) return fail(CAP_E_INVALID, "plan or out is NULL");
+  *out = p->cfg;
+  return CAP_OK;
+}

@@ -1,0 +1,204 @@
+"""Fixed-rate serving loop with continuous batching over a batched plan.
+
+The paper predicts its k humans one after another every cycle (Sec. IV-B);
+here every cycle is one batched plan run (hipGraphs: belief update of every
+active human from its newest observation, grid clear, one persistent rollout
+launch, normalisation).  Humans arrive and leave while cycles are in flight:
+
+* admission -- an arriving human waits until a slot is free and the particle
+  budget (total particles in flight per cycle, which bounds the cycle time)
+  has room for its N; it then joins at the next cycle boundary;
+* overlap -- consecutive cycles go to alternating streams and use alternating
+  ring entries of every per-cycle buffer, so cycle c+1 can start on the device
+  while cycle c is still running; only the tiny belief updates are ordered;
+* latency -- a cycle's latency is the time from its release tick until the
+  host observes its completion event (polled, never a blocking wait).
+
+Results are keyed by (human id, cycle, seed) alone, so a human's grids are the
+same whether it is served alone or in any mix.  Slot buffers are allocated
+once up front (no allocation in the loop).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import capred
+
+
+@dataclasses.dataclass
+class HumanRequest:
+    hid: int
+    model: capred.Model
+    grid: Sequence
+    N: int
+    H: int
+    last_xy: Sequence[float]
+    log_belief: Optional[np.ndarray] = None   # carried state; None = uniform prior
+
+
+@dataclasses.dataclass
+class CycleRecord:
+    cycle: int
+    release: float
+    done_event: torch.cuda.Event
+    humans: List[int]
+    particle_steps: int
+    completed: Optional[float] = None
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.completed is None else self.completed - self.release
+
+
+class Server:
+    def __init__(self, K: int, speed: float, dt: float, n_slots: int, max_H: int, max_nx: int,
+                 max_ny: int, max_G: int, max_B: int, ring: int = 2, n_streams: int = 2,
+                 particle_budget: Optional[int] = None, seed: int = 0, probs: bool = True,
+                 tuning: Optional[dict] = None, device="cuda"):
+        tuning = tuning or {}
+        self.plan = capred.Plan(K, speed, dt, n_slots, max_obs=1, ring=ring, **tuning)
+        self.K, self.ring, self.seed = K, ring, seed
+        self.max = (max_H, max_nx, max_ny, max_G, max_B)
+        cells = max_H * max_nx * max_ny
+        self.pool_counts = torch.zeros((n_slots, ring * cells), dtype=torch.int32, device=device)
+        self.pool_probs = (torch.zeros((n_slots, ring * cells), dtype=torch.float32, device=device)
+                           if probs else None)
+        self.pool_off = torch.zeros((n_slots, ring * max_H), dtype=torch.int32, device=device)
+        self.pool_lb = torch.zeros((n_slots, max_G * max_B), dtype=torch.float64, device=device)
+        self.pool_b = torch.zeros((n_slots, ring * max_G * max_B), dtype=torch.float64,
+                                  device=device)
+        self.free: List[int] = list(range(n_slots))
+        self.slot_of: Dict[int, int] = {}
+        self.req: Dict[int, HumanRequest] = {}
+        self.waiting: collections.deque = collections.deque()
+        self.budget = particle_budget
+        self.in_use = 0
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.cycle = 0
+        self.records: List[CycleRecord] = []
+        self._pending: collections.deque = collections.deque()
+
+    # ----------------------------------------------------------- admission
+    def submit(self, r: HumanRequest):
+        H, nx, ny = r.H, int(r.grid[3]), int(r.grid[4])
+        if H > self.max[0] or nx > self.max[1] or ny > self.max[2] or r.model.G > self.max[3] \
+                or r.model.B > self.max[4] or r.model.K != self.K:
+            raise ValueError(f"human {r.hid} exceeds the slot capacity of this server")
+        self.waiting.append(r)
+
+    def depart(self, hid: int):
+        if hid in self.slot_of:
+            s = self.slot_of.pop(hid)
+            self.plan.retire(s)
+            self.in_use -= self.req.pop(hid).N
+            self.free.append(s)
+        else:
+            self.waiting = collections.deque(r for r in self.waiting if r.hid != hid)
+
+    def _views(self, s: int, r: HumanRequest) -> capred.SlotBuffers:
+        R, H, nx, ny = self.ring, r.H, int(r.grid[3]), int(r.grid[4])
+        G, B = r.model.G, r.model.B
+        n = R * H * ny * nx
+        return capred.SlotBuffers(
+            self.pool_counts[s, :n].view(R, H, ny, nx),
+            None if self.pool_probs is None else self.pool_probs[s, :n].view(R, H, ny, nx),
+            self.pool_off[s, :R * H].view(R, H),
+            self.pool_lb[s, :G * B].view(G, B),
+            self.pool_b[s, :R * G * B].view(R, G, B))
+
+    def _admit_waiting(self):
+        kept = collections.deque()
+        while self.waiting:
+            r = self.waiting.popleft()
+            fits = self.budget is None or self.in_use + r.N <= self.budget
+            if self.free and fits:
+                s = self.free.pop(0)
+                buf = self._views(s, r)
+                if r.log_belief is not None:
+                    buf.log_belief.copy_(torch.as_tensor(r.log_belief, dtype=torch.float64))
+                self.plan.admit(s, r.hid, r.model, r.grid, r.N, r.H, r.last_xy, buf,
+                                reset_belief=r.log_belief is None)
+                self.slot_of[r.hid] = s
+                self.req[r.hid] = r
+                self.in_use += r.N
+            else:
+                kept.append(r)
+        self.waiting = kept
+
+    # ----------------------------------------------------------- cycles
+    def step(self, observations: Dict[int, Sequence[float]], release: Optional[float] = None,
+             plain: bool = False) -> CycleRecord:
+        """Admits waiting humans, stages each active human's new position and
+        launches one cycle (batched, or the per-human reference if plain)."""
+        self._admit_waiting()
+        for hid, xy in observations.items():
+            if hid in self.slot_of:
+                self.plan.stage(self.slot_of[hid], xy)
+        stream = self.streams[self.cycle % len(self.streams)]
+        ev = torch.cuda.Event()
+        with torch.cuda.stream(stream):
+            if plain:
+                self.plan.run_plain(self.seed, self.cycle)
+            else:
+                self.plan.run(self.seed, self.cycle)
+            ev.record(stream)
+        rec = CycleRecord(self.cycle, time.perf_counter() if release is None else release, ev,
+                          sorted(self.slot_of), sum(self.req[h].N * self.req[h].H
+                                                    for h in self.slot_of))
+        self.records.append(rec)
+        self._pending.append(rec)
+        self.cycle += 1
+        return rec
+
+    def poll(self) -> int:
+        """Marks finished cycles (non-blocking); returns how many are still pending."""
+        now = time.perf_counter()
+        while self._pending and self._pending[0].done_event.query():
+            self._pending.popleft().completed = now
+        return len(self._pending)
+
+    def drain(self):
+        while self.poll():
+            time.sleep(20e-6)
+
+    def grids(self, hid: int, cycle: int):
+        """(counts [H,ny,nx], probs, offgrid, posterior [G,B]) of `hid` at `cycle`
+        (valid until that ring entry is reused)."""
+        s = self.slot_of[hid]
+        r = self.req[hid]
+        b = self._views(s, r)
+        e = cycle % self.ring
+        return (b.counts[e], None if b.probs is None else b.probs[e], b.offgrid[e], b.belief[e])
+
+    def close(self):
+        self.plan.sync()
+        self.plan.close()
+
+
+def run_paced(server: Server, obs_fn, n_cycles: int, rate_hz: float = 125.0,
+              progress=None) -> np.ndarray:
+    """Fixed-rate loop: cycle c is released at t0 + c/rate; the host spins on
+    event queries between ticks.  obs_fn(c) -> {hid: xy}.  Returns latencies (s)."""
+    period = 1.0 / rate_hz
+    t0 = time.perf_counter() + 2 * period
+    first = len(server.records)
+    for c in range(n_cycles):
+        tick = t0 + c * period
+        while True:
+            server.poll()
+            now = time.perf_counter()
+            if now >= tick:
+                break
+            if tick - now > 200e-6:
+                time.sleep(min(tick - now - 150e-6, 1e-3))
+        server.step(obs_fn(c), release=tick)
+        if progress and (c + 1) % progress[0] == 0:
+            progress[1](c + 1)
+    server.drain()
+    return np.array([r.latency for r in server.records[first:]], np.float64)

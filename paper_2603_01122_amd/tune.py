@@ -1,0 +1,96 @@
+"""Autotuner of the batched rollout launch.
+
+Times each candidate (threads per block, particles per thread, LDS window
+bytes) on the actual workload -- a few serving cycles of the given humans --
+and returns the fastest.  Results are cached per device and workload
+signature in a JSON file so that a server pays the search once.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import capred
+from .serve import HumanRequest, Server
+
+CANDIDATES: List[Dict[str, int]] = [
+    dict(block_threads=b, particles_per_thread=p)
+    for b in (256, 512, 1024) for p in (1, 2, 4)
+]
+
+CACHE = os.environ.get("CAPRED_TUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "capred_tune.json"))
+
+
+def signature(humans, plain: bool) -> str:
+    key = json.dumps({
+        "device": torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none",
+        "cus": capred.device_cu_count(),
+        "plain": plain,
+        "humans": [(h.K, h.N, h.H, h.G, h.B, tuple(h.grid)) for h in humans],
+    }, sort_keys=True)
+    return hashlib.sha1(key.encode()).hexdigest()
+
+
+def time_candidate(humans, tracks: Dict[int, np.ndarray], cand: Dict[str, int], cycles: int = 6,
+                   warmup: int = 3, plain: bool = False) -> float:
+    """Seconds per cycle of the candidate (wall clock, back-to-back cycles)."""
+    h0 = humans[0]
+    srv = Server(h0.K, h0.speed, h0.dt, len(humans), max(h.H for h in humans),
+                 max(h.grid[3] for h in humans), max(h.grid[4] for h in humans),
+                 max(h.G for h in humans), max(h.B for h in humans), tuning=cand)
+    try:
+        for h in humans:
+            srv.submit(HumanRequest(h.hid, capred.model_of(h), h.grid, h.N, h.H,
+                                    tracks[h.hid][0]))
+        for c in range(warmup):
+            srv.step({h.hid: tracks[h.hid][c + 1] for h in humans}, plain=plain)
+        srv.drain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in range(warmup, warmup + cycles):
+            srv.step({h.hid: tracks[h.hid][c + 1] for h in humans}, plain=plain)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / cycles
+    finally:
+        srv.close()
+
+
+def autotune(humans, tracks: Dict[int, np.ndarray], candidates: Optional[Sequence[dict]] = None,
+             plain: bool = False, use_cache: bool = True, cycles: int = 6):
+    """Returns (best candidate, {str(candidate): seconds per cycle})."""
+    sig = signature(humans, plain)
+    cache = {}
+    if use_cache and os.path.exists(CACHE):
+        try:
+            cache = json.load(open(CACHE))
+        except (OSError, ValueError):
+            cache = {}
+        if sig in cache:
+            return cache[sig]["best"], cache[sig]["table"]
+    table = {}
+    best, best_t = None, float("inf")
+    for cand in (candidates or CANDIDATES):
+        try:
+            t = time_candidate(humans, tracks, cand, cycles=cycles, plain=plain)
+        except capred.CapError:
+            continue   # e.g. the LDS window does not fit this block shape
+        table[json.dumps(cand, sort_keys=True)] = t
+        if t < best_t:
+            best, best_t = dict(cand), t
+    if best is None:
+        raise RuntimeError("no tuning candidate could run")
+    if use_cache:
+        cache[sig] = {"best": best, "table": table}
+        try:
+            os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+            json.dump(cache, open(CACHE, "w"), indent=1)
+        except OSError:
+            pass
+    return best, table

@@ -1,0 +1,239 @@
+"""GPU tests of the batched plan and the serving loop.
+
+* batched == per-human reference launches == single-human entry point, bit for
+  bit (same kernels' arithmetic, same keys);
+* full-size many-human workload (16 humans, 2^14..2^18 particles, H=100) in
+  the launch configuration the benchmark times: posteriors within 1e-5 of the
+  oracle for every human; histograms within the tie rule for sampled humans;
+  counting invariant for every human;
+* continuous batching: a human's grids are identical alone and in a changing
+  mix; two overlapping streams give the same results as one.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_01122_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cap():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_01122_amd import capred
+    return capred
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def tracks_for(orc, humans, T):
+    out = {}
+    for h in humans:
+        _, pos = orc.simulate_tracks(K=h.K, speed=h.speed, dt=h.dt, frame=h.frame,
+                                     start=np.array([h.start]), beta=[h.true_beta],
+                                     goal=h.goals[h.true_goal][None], T=T, seed=0, stream=h.hid)
+        out[h.hid] = pos[0]
+    return out
+
+
+def small_scene(n=6, N_div=16, H=30):
+    sc = scenes.config3()
+    hs = sc.humans[:n]
+    for h in hs:
+        h.N = max(1, h.N // N_div) + 37  # ragged
+        h.H = H
+    return hs
+
+
+def make_server(cap, humans, ring=2, n_streams=2, slots=None, **tuning):
+    from paper_2603_01122_amd.serve import Server
+    h0 = humans[0]
+    return Server(h0.K, h0.speed, h0.dt, slots or len(humans), max(h.H for h in humans),
+                  max(h.grid[3] for h in humans), max(h.grid[4] for h in humans),
+                  max(h.G for h in humans), max(h.B for h in humans), ring=ring,
+                  n_streams=n_streams, tuning=tuning or None)
+
+
+def request(cap, h, last):
+    from paper_2603_01122_amd.serve import HumanRequest
+    return HumanRequest(h.hid, cap.model_of(h), h.grid, h.N, h.H, last)
+
+
+def snapshot(srv, hid, c):
+    counts, probs, off, post = srv.grids(hid, c)
+    torch.cuda.synchronize()
+    return (counts.cpu().numpy().copy(), probs.cpu().numpy().copy(), off.cpu().numpy().copy(),
+            post.cpu().numpy().copy())
+
+
+def test_batched_equals_plain_and_single(orc, cap):
+    humans = small_scene()
+    tr = tracks_for(orc, humans, 8)
+    note("batched vs plain vs single, 6 humans x 4 cycles")
+    A = make_server(cap, humans)
+    Bp = make_server(cap, humans)
+    for h in humans:
+        A.submit(request(cap, h, tr[h.hid][0]))
+        Bp.submit(request(cap, h, tr[h.hid][0]))
+    for c in range(4):
+        obs = {h.hid: tr[h.hid][c + 1] for h in humans}
+        A.step(obs)
+        Bp.step(obs, plain=True)
+        A.drain()
+        Bp.drain()
+        for h in humans:
+            a = snapshot(A, h.hid, c)
+            b = snapshot(Bp, h.hid, c)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (c, h.hid)
+            # the single-human entry point with the plan's posterior and start
+            post = torch.tensor(a[3], device="cuda")
+            out = cap.predict_occupancy(cap.model_of(h), h.grid, tuple(tr[h.hid][c + 1].astype(float)),
+                                        post, h.N, h.H, seed=0, human_id=h.hid, cycle=c)
+            torch.cuda.synchronize()
+            assert np.array_equal(out["counts"].cpu().numpy(), a[0])
+            assert np.array_equal(out["offgrid"].cpu().numpy(), a[2])
+            assert np.array_equal(cap.normalize(out["counts"], h.N).cpu().numpy(), a[1])
+            assert np.all(a[0].reshape(h.H, -1).sum(1) + a[2] == h.N)
+    A.close()
+    Bp.close()
+
+
+def test_full_size_many_humans_parity(orc, cap):
+    sc = scenes.config3()
+    humans = sc.humans
+    n_pre = 3
+    tr = tracks_for(orc, humans, n_pre + 1)
+    note("config3 full size: 16 humans, 3 cycles")
+    srv = make_server(cap, humans)
+    for h in humans:
+        srv.submit(request(cap, h, tr[h.hid][0]))
+    for c in range(n_pre):
+        srv.step({h.hid: tr[h.hid][c + 1] for h in humans})
+    srv.drain()
+    c = n_pre - 1
+    snaps = {h.hid: snapshot(srv, h.hid, c) for h in humans}
+    for h in humans:
+        counts, probs, off, post = snaps[h.hid]
+        assert np.all(counts.reshape(h.H, -1).sum(1) + off == h.N)
+        lb_o, b_o, _ = orc.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta,
+                                         goals=h.goals, obs=tr[h.hid][:n_pre + 1])
+        assert np.max(np.abs(np.log(post) - lb_o)) <= 1e-5
+    # histogram parity under the tie rule for the smallest and a mid-size human.
+    # The oracle predicts from its own posterior; the GPU's posterior agrees to
+    # 1e-5 in log, so its pair-CDF boundaries agree to 1e-5 (pair window).
+    order = sorted(humans, key=lambda h: h.N)
+    for h in (order[0], order[len(order) // 2]):
+        counts, probs, off, post = snaps[h.hid]
+        z0 = tuple(tr[h.hid][n_pre].astype(float))
+        note(f"oracle human {h.hid} N={h.N}")
+        single = cap.predict_occupancy(cap.model_of(h), h.grid, z0,
+                                       torch.tensor(post, device="cuda"), h.N, h.H, seed=0,
+                                       human_id=h.hid, cycle=c, trace=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(single["counts"].cpu().numpy(), counts)
+        _, b_o, _ = orc.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals,
+                                      obs=tr[h.hid][:n_pre + 1])
+        kw = dict(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals, grid=h.grid,
+                  z0=z0, belief=b_o.reshape(-1), N=h.N, H=h.H, seed=0, human=h.hid, cycle=c)
+        ref = orc.predict(**kw)
+        st, first = orc.tie_check(other_pair=single["trace_pair"].cpu().numpy(),
+                                  other_k=single["trace_k"].cpu().numpy(), window=1e-6,
+                                  pair_window=1e-5, **kw)
+        assert np.count_nonzero(st == 2) == 0
+        for t in range(h.H):
+            budget = 2 * np.count_nonzero((st == 1) & (first <= t + 1))
+            d = np.abs(counts[t].astype(np.int64) - ref["counts"][t]).sum() + \
+                abs(int(off[t]) - int(ref["offgrid"][t]))
+            assert d <= budget
+            assert 0.5 * d / h.N <= 1e-3
+        print(f"human {h.hid}: flagged {np.count_nonzero(st == 1)} of {h.N}")
+    srv.close()
+
+
+def test_continuous_batching_invariance(orc, cap):
+    humans = small_scene(n=5, N_div=8, H=25)
+    tr = tracks_for(orc, humans, 12)
+    x = humans[2]
+    note("alone vs churning mix")
+    alone = make_server(cap, [x], slots=1)
+    alone.submit(request(cap, x, tr[x.hid][0]))
+    mix = make_server(cap, humans, slots=3)  # fewer slots than humans: some wait
+    mix.submit(request(cap, humans[0], tr[humans[0].hid][0]))
+    mix.submit(request(cap, x, tr[x.hid][0]))
+    got_alone, got_mix = [], []
+    for c in range(8):
+        if c == 2:
+            mix.submit(request(cap, humans[1], tr[humans[1].hid][c]))
+            mix.submit(request(cap, humans[3], tr[humans[3].hid][c]))  # waits for a slot
+        if c == 4:
+            mix.depart(humans[0].hid)                                  # frees a slot
+        if c == 6:
+            mix.depart(humans[1].hid)
+            mix.submit(request(cap, humans[4], tr[humans[4].hid][c]))
+        alone.step({x.hid: tr[x.hid][c + 1]})
+        mix.step({h.hid: tr[h.hid][c + 1] for h in humans})
+        alone.drain()
+        mix.drain()
+        got_alone.append(snapshot(alone, x.hid, c))
+        got_mix.append(snapshot(mix, x.hid, c))
+    assert humans[3].hid in mix.slot_of and humans[4].hid in mix.slot_of
+    for a, b in zip(got_alone, got_mix):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+    alone.close()
+    mix.close()
+
+
+def test_two_streams_overlap_equals_one(orc, cap):
+    humans = small_scene(n=4, N_div=4, H=40)
+    tr = tracks_for(orc, humans, 10)
+    note("ring 2 / two streams vs ring 1 / one stream")
+    one = make_server(cap, humans, ring=1, n_streams=1)
+    two = make_server(cap, humans, ring=2, n_streams=2)
+    for s in (one, two):
+        for h in humans:
+            s.submit(request(cap, h, tr[h.hid][0]))
+    res1, res2 = [], []
+    for c in range(6):
+        obs = {h.hid: tr[h.hid][c + 1] for h in humans}
+        one.step(obs)
+        one.drain()
+        res1.append([snapshot(one, h.hid, c) for h in humans])
+        two.step(obs)
+        if c % 2 == 1:  # two cycles in flight before reading
+            two.drain()
+            res2.append([snapshot(two, h.hid, c - 1) for h in humans])
+            res2.append([snapshot(two, h.hid, c) for h in humans])
+    for a, b in zip(res1, res2):
+        for x, y in zip(a, b):
+            for u, v in zip(x, y):
+                assert np.array_equal(u, v)
+    one.close()
+    two.close()
+
+
+def test_plan_errors(cap):
+    p = cap.Plan(16, 1.2, 0.02, 2, max_obs=1)
+    h = scenes.config3().humans[0]
+    buf = cap.SlotBuffers.allocate(cap.model_of(h), h.grid, 5, 2)
+    p.admit(0, 1, cap.model_of(h), h.grid, 100, 5, h.start, buf)
+    with pytest.raises(cap.CapError):
+        p.admit(0, 2, cap.model_of(h), h.grid, 100, 5, h.start, buf)   # occupied
+    p.stage(0, [h.start])
+    with pytest.raises(cap.CapError):
+        p.stage(0, [h.start])                                          # > max_obs
+    with pytest.raises(cap.CapError):
+        p.stage(1, [h.start])                                          # empty slot
+    with pytest.raises(cap.CapError):
+        p.run(0, 0x7FFFFFFF)
+    p.run(0, 0)
+    p.sync()
+    p.close()
