@@ -2,7 +2,7 @@
 """Benchmark of the serving cycle on the 16-human workload.
 
 Workload: 16 humans with particle counts log-uniform in [2^14, 2^18]
-(about 1.42e6 particles), 2-6 goals each, 9 beta values, 16 headings at
+(about 1.5e6 particles), 2-6 goals each, 9 beta values, 16 headings at
 1.2 m/s, dt = 0.02 s, H = 100 steps, one 256x256 grid (0.05 m) per human.
 One step = one serving cycle over all humans: a new observed position per
 human, belief update, grid clear, one persistent batched rollout launch
@@ -40,14 +40,16 @@ def log(msg):
 def algorithmic_ops(K: int, r: dict) -> float:
     """Minimal VALU work per particle-step of the stable-form rollout, in
     full-rate lane-operation equivalents (rates r from the probes):
-      per heading: 2 FMA (2a.s_k + |s_k|^2), add (D^2 + n), add (d + D),
-                   2 mul (quotient, beta scale), add (prefix), compare+count
-                   = 9 full-rate, plus sqrt, reciprocal, exp2;
-      per step:    offset/convert/|a|^2/2a/uniform/threshold/step/cell/bounds
-                   = 22 full-rate plus one sqrt (|a|);
+      per heading: 2 FMA (n_k = 2a.s_k + |s_k|^2), add (|a|^2 + n_k),
+                   FMA (scaled denominator), mul (exponent), add (prefix sum)
+                   = 5 full-rate, plus sqrt, reciprocal and exp2;
+      inverse CDF: binary search, log2(K) compare + select pairs;
+      per step:    offset/convert/|a|^2/|a|/2a/uniform/threshold/step/cell/
+                   bounds = 22 full-rate plus one sqrt;
       Philox:      one 10-round block per 4 steps = 5 wide multiplies and
                    10 full-rate ops per step."""
-    return (K * (9 + r["sqrt"] + r["rcp"] + r["exp2"]) + 22 + r["sqrt"] + 10 + 5 * r["mul64"])
+    return (K * (5 + r["sqrt"] + r["rcp"] + r["exp2"]) + 2 * math.log2(K) + 22 + r["sqrt"]
+            + 10 + 5 * r["mul64"])
 
 
 def measure_rates(capred, torch) -> dict:
@@ -95,16 +97,25 @@ def make_server(capred, humans, tuning, tracks):
     return srv
 
 
-def cpu_baseline(scene, tracks_np, max_seconds):
+def cpu_baseline(scene, max_seconds):
     """The FP64 oracle on one full serving cycle (belief update + Alg. 1 for all
-    humans), on every host core this process may use."""
+    humans), on every host core this process may use.  Its observations come
+    from its own track simulator."""
+    import numpy as np
     import oracle
     threads = oracle.default_threads()
+    sims = {}
+    for h in scene.humans:
+        _, pos = oracle.simulate_tracks(K=h.K, speed=h.speed, dt=h.dt, frame=h.frame,
+                                        start=np.array([h.start]), beta=[h.true_beta],
+                                        goal=h.goals[h.true_goal][None], T=1, seed=0,
+                                        stream=h.hid)
+        sims[h.hid] = pos[0]
     t0 = time.perf_counter()
     steps = 0
     done = 0
     for h in scene.humans:
-        obs = tracks_np[h.hid][:2]
+        obs = sims[h.hid]
         _, b, _ = oracle.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals,
                                        obs=obs)
         oracle.predict(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals, grid=h.grid,
@@ -133,6 +144,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="JSON launch shape for the batched rollout (skips its autotuning)")
+    ap.add_argument("--plain-tuning", type=str, default=None,
+                    help="JSON launch shape for the plain launches (skips their autotuning)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain copy of this many MiB (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no "
@@ -156,12 +173,21 @@ def main():
     rates = measure_rates(capred, torch)
     log(f"probe rates (cost relative to FMA): { {k: round(v, 3) for k, v in rates.items() if k != 'fma_lane_ops_per_s'} }")
 
-    if args.no_tune:
-        best, table, best_plain, table_plain = {}, {}, {}, {}
-    else:
-        best, table = tune.autotune(humans, tracks, use_cache=False)
-        best_plain, table_plain = tune.autotune(humans, tracks, plain=True, use_cache=False,
-                                                cycles=3)
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        capred.copy(a, b)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read and written by copy_kernel")
+        del a, b
+    best = json.loads(args.tuning) if args.tuning else ({} if args.no_tune else None)
+    best_plain = (json.loads(args.plain_tuning) if args.plain_tuning
+                  else ({} if args.no_tune else None))
+    if best is None:
+        best, _ = tune.autotune(humans, tracks, use_cache=False)
+    if best_plain is None:
+        best_plain, _ = tune.autotune(humans, tracks, plain=True, use_cache=False, cycles=3)
     log(f"tuned batched: {best}  plain: {best_plain}")
 
     # ---------------------------------------------------------- batched, back-to-back
@@ -236,7 +262,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one full cycle)")
-        cpu = cpu_baseline(scene, tracks, args.cpu_seconds)
+        cpu = cpu_baseline(scene, args.cpu_seconds)
 
     latency = None
     if lat is not None:

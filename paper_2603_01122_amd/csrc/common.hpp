@@ -79,16 +79,15 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    // one v_mad_u64_u32 per product gives both halves
+    const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+    const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = (uint32_t)p1;
     c2 = n2;
-    c3 = lo0;
+    c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -115,21 +114,66 @@ struct HeadingTable {
   float s2[CAP_MAX_K];
 };
 
-// Boltzmann heading draw at lattice offset a = x - g (lattice units) with
-// nb = -beta q log2(e).  The logit of heading k is beta (d_0 - d_k) up to a
-// constant; it is computed from the cancellation-free difference
-//   Delta_k = |a + s_k| - |a| = (2 a.s_k + |s_k|^2) / (|a + s_k| + |a|),
-// so its absolute error stays a few ulp of the step length however far the
-// goal is.  Weights w_k = exp2(nb Delta_k) (optionally shifted by the largest
-// exponent), prefix sums C_k, and k = #{k < K-1 : C_k <= u C_{K-1}}, which is
-// min{k : u C_{K-1} < C_k} because C is non-decreasing.
+// Inverse CDF over K non-decreasing prefix sums: #{k < K-1 : C_k <= thr},
+// which equals min{k : thr < C_k} (capped at K-1).  For K a power of two the
+// count is found by a branchless binary search whose register selections are
+// explicit conditional moves (per-lane dynamic indexing of registers would
+// spill to scratch); otherwise by counting.
 template <int KT>
-__device__ __forceinline__ int draw_heading(float ax, float ay, float nb, float u, bool shift,
+__device__ __forceinline__ int cdf_index(const float* C, float thr, int Krt) {
+  constexpr bool kPow2 = KT >= 4 && (KT & (KT - 1)) == 0;
+  if constexpr (kPow2) {
+    // Level l probes C[c * (KT >> l) + (KT >> (l + 1)) - 1] where the bits
+    // b_0..b_{l-1} decided so far spell c (b_0 most significant); the probe is
+    // picked by a tree of 2^l - 1 conditional moves on those bits.
+    constexpr int L = KT == 4 ? 2 : KT == 8 ? 3 : KT == 16 ? 4 : KT == 32 ? 5 : 6;
+    bool b[L];
+    int pos = 0;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      float v[KT / 2];
+#pragma unroll
+      for (int c = 0; c < (1 << l); ++c) v[c] = C[c * (KT >> l) + (KT >> (l + 1)) - 1];
+#pragma unroll
+      for (int st = l - 1; st >= 0; --st)
+#pragma unroll
+        for (int j = 0; j < (1 << st); ++j) v[j] = b[st] ? v[2 * j + 1] : v[2 * j];
+      b[l] = v[0] <= thr;
+      pos += b[l] ? (KT >> (l + 1)) : 0;
+    }
+    return pos;
+  } else {
+    constexpr int KM = KT > 0 ? KT : CAP_MAX_K;
+    const int K = KT > 0 ? KT : Krt;
+    int kk = 0;
+#pragma unroll
+    for (int k = 0; k < KM - 1; ++k) {
+      if (KT == 0 && k >= K - 1) break;
+      kk += (C[k] <= thr) ? 1 : 0;
+    }
+    return kk;
+  }
+}
+
+// Boltzmann heading draw at lattice offset a = x - g (lattice units).  The
+// logit of heading k is beta (|a| - |a + s_k|) (shift-invariant form of
+// beta Q_k); it is computed from the cancellation-free difference
+//   Delta_k = |a + s_k| - |a| = n_k / (|a + s_k| + |a|),  n_k = 2 a.s_k + |s_k|^2,
+// whose absolute error stays a few ulp of the step length however far the
+// goal is.  With nb = -beta q log2(e) and ib = 1/nb (both per particle), the
+// base-2 exponent nb Delta_k is n_k / (|a + s_k| ib + |a| ib): one FMA, one
+// reciprocal and one multiply.  |a + s_k|^2 = |a|^2 + n_k is taken through
+// |.| (a free source modifier) against rounding below zero at the goal.
+// Weights w_k = exp2(exponent) (optionally shifted by the largest exponent),
+// prefix sums C_k, heading = cdf_index(C, u C_{K-1}).
+template <int KT>
+__device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float u, bool shift,
                                             const HeadingTable& T, int Krt) {
   constexpr int KM = KT > 0 ? KT : CAP_MAX_K;
   const int K = KT > 0 ? KT : Krt;
   const float D2 = fmaf(ax, ax, ay * ay);
   const float D = fast_sqrt(D2);
+  const float Dib = D * ib;
   const float ax2 = ax + ax, ay2 = ay + ay;
   float C[KM];
   float acc = 0.f;
@@ -138,9 +182,8 @@ __device__ __forceinline__ int draw_heading(float ax, float ay, float nb, float 
     for (int k = 0; k < KM; ++k) {
       if (KT == 0 && k >= K) break;
       const float n = fmaf(ax2, T.fx[k], fmaf(ay2, T.fy[k], T.s2[k]));
-      const float d = fast_sqrt(fmaxf(D2 + n, 0.f));
-      const float l = n * fast_rcp(d + D);
-      acc += fast_exp2(nb * l);
+      const float d = fast_sqrt(fabsf(D2 + n));
+      acc += fast_exp2(n * fast_rcp(fmaf(d, ib, Dib)));
       C[k] = acc;
     }
   } else {
@@ -149,8 +192,8 @@ __device__ __forceinline__ int draw_heading(float ax, float ay, float nb, float 
     for (int k = 0; k < KM; ++k) {
       if (KT == 0 && k >= K) break;
       const float n = fmaf(ax2, T.fx[k], fmaf(ay2, T.fy[k], T.s2[k]));
-      const float d = fast_sqrt(fmaxf(D2 + n, 0.f));
-      C[k] = nb * (n * fast_rcp(d + D));
+      const float d = fast_sqrt(fabsf(D2 + n));
+      C[k] = n * fast_rcp(fmaf(d, ib, Dib));
       m = fmaxf(m, C[k]);
     }
 #pragma unroll
@@ -160,14 +203,7 @@ __device__ __forceinline__ int draw_heading(float ax, float ay, float nb, float 
       C[k] = acc;
     }
   }
-  const float thr = u * acc;
-  int kk = 0;
-#pragma unroll
-  for (int k = 0; k < KM - 1; ++k) {
-    if (KT == 0 && k >= K - 1) break;
-    kk += (C[k] <= thr) ? 1 : 0;
-  }
-  return kk;
+  return cdf_index<KT>(C, u * acc, Krt);
 }
 
 }  // namespace capred

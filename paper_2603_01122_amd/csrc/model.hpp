@@ -111,7 +111,7 @@ inline cap_status make_rollout_desc(int K, double speed, double dt, int B, const
     return fail(CAP_E_INVALID, "grid size + H steps exceed the int32 lattice");
   double max_beta = 0.0;
   for (int b = 0; b < B; ++b) {
-    d.nbeta[b] = (float)(-(double)beta[b] * q * (double)kLog2e);
+    d.ibeta[b] = (float)(1.0 / (-(double)beta[b] * q * (double)kLog2e));
     max_beta = std::max(max_beta, (double)beta[b]);
   }
   d.shift = max_beta * speed * dt > kNoShiftLimit ? 1 : 0;

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256)
   int32_t Y = (int32_t)rint((start[2 * r + 1] - y0) / q);
   const int32_t GX = (int32_t)rint(((double)goal[2 * r] - x0) / q);
   const int32_t GY = (int32_t)rint(((double)goal[2 * r + 1] - y0) / q);
-  const float nb = (float)(-(double)beta[r] * q * (double)kLog2e);
+  const float ib = (float)(1.0 / (-(double)beta[r] * q * (double)kLog2e));
   const bool shift = (double)beta[r] * (double)d.Rx * q > kNoShiftLimit ||
                      (double)beta[r] * (double)d.Ry * q > kNoShiftLimit || d.shift;
   uint4 w = make_uint4(0u, 0u, 0u, 0u);
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256)
       if (s == 0) w = philox10((uint32_t)r, (uint32_t)((t - 1) >> 2), stream_id, 0xFFFFFFFFu,
                                seed_lo, seed_hi);
       const float u = uniform24f(pick_word(w, s));
-      const int k = draw_heading<KT>((float)(X - GX), (float)(Y - GY), nb, u, shift, d.T, d.K);
+      const int k = draw_heading<KT>((float)(X - GX), (float)(Y - GY), ib, u, shift, d.T, d.K);
       X += d.Sx[k];
       Y += d.Sy[k];
     }

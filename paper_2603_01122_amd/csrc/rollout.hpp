@@ -18,7 +18,7 @@ struct RolloutDesc {
   int32_t shift;            // 1: subtract the largest exponent (large beta * step)
   HeadingTable T;           // lattice-unit steps and squared lengths (FP32)
   int32_t Sx[CAP_MAX_K], Sy[CAP_MAX_K];
-  float nbeta[CAP_MAX_B];   // -beta * q * log2(e)
+  float ibeta[CAP_MAX_B];   // 1 / (-beta q log2(e)), q = lattice pitch
   int32_t GX[CAP_MAX_G], GY[CAP_MAX_G];
   const double* belief;     // [G][B]
   uint32_t* counts;         // [H][ny][nx]
@@ -31,7 +31,7 @@ struct TileShared {
   double P[CAP_MAX_J];      // pair CDF (sequential FP64 prefix sums)
   int2 S[CAP_MAX_K];        // lattice steps for the dynamic heading index
   int2 goal[CAP_MAX_G];
-  float nbeta[CAP_MAX_B];
+  float ibeta[CAP_MAX_B];
   uint32_t off[2];          // off-grid counters of the two in-flight steps
   int last_pos;
 };
@@ -68,7 +68,7 @@ __device__ __forceinline__ uint32_t pick_word(const uint4& w, int s) {
 // Processes particles [first, first + P * blockDim.x) of human d (clipped to N).
 // win: 2 * cap words of LDS, zero on entry and on exit.
 template <int KT, int P>
-__device__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_lo,
+__device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_lo,
                              uint32_t seed_hi, TileShared& sh, uint32_t* win, int cap) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
@@ -89,7 +89,7 @@ __device__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_
   }
   for (int k = tid; k < d.K; k += nthr) sh.S[k] = make_int2(d.Sx[k], d.Sy[k]);
   for (int g = tid; g < d.G; g += nthr) sh.goal[g] = make_int2(d.GX[g], d.GY[g]);
-  for (int b = tid; b < d.B; b += nthr) sh.nbeta[b] = d.nbeta[b];
+  for (int b = tid; b < d.B; b += nthr) sh.ibeta[b] = d.ibeta[b];
   __syncthreads();
 
   // ---- per-particle (beta, g) draw, held for the whole horizon
@@ -97,7 +97,7 @@ __device__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_
   int64_t idx[P];
   bool act[P];
   int32_t X[P], Y[P], GXp[P], GYp[P];
-  float nb[P];
+  float ib[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     idx[p] = first + (int64_t)p * nthr + tid;
@@ -106,7 +106,7 @@ __device__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_
     Y[p] = d.Y0;
     GXp[p] = 0;
     GYp[p] = 0;
-    nb[p] = 0.f;
+    ib[p] = 1.f;
     if (act[p]) {
       const uint4 w = philox10((uint32_t)idx[p], 0u, d.human, c3_pair, seed_lo, seed_hi);
       const double u = uniform24d(w.x);
@@ -120,7 +120,7 @@ __device__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_
       const int g = j / d.B, b = j - g * d.B;
       GXp[p] = sh.goal[g].x;
       GYp[p] = sh.goal[g].y;
-      nb[p] = sh.nbeta[b];
+      ib[p] = sh.ibeta[b];
       if (d.trace_pair) d.trace_pair[idx[p]] = j;
     }
   }
@@ -147,7 +147,7 @@ __device__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_
       bool off = false;
       if (act[p]) {
         const float u = uniform24f(pick_word(rw[p], s));
-        const int k = draw_heading<KT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), nb[p], u,
+        const int k = draw_heading<KT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p], u,
                                        shift, d.T, d.K);
         const int2 st = sh.S[k];
         X[p] += st.x;
