@@ -38,18 +38,26 @@ def log(msg):
 
 
 def algorithmic_ops(K: int, r: dict) -> float:
-    """Minimal VALU work per particle-step of the stable-form rollout, in
-    full-rate lane-operation equivalents (rates r from the probes):
-      per heading: 2 FMA (n_k = 2a.s_k + |s_k|^2), add (|a|^2 + n_k),
-                   FMA (scaled denominator), mul (exponent), add (prefix sum)
-                   = 5 full-rate, plus sqrt, reciprocal and exp2;
+    """Minimal VALU time per particle-step of the stable-form rollout, in
+    full-rate lane-operation slots (one FP32 FMA = 1; rates r from the probes).
+    Operation counts of the algorithm:
+      per heading: dot product shared by the two opposite headings (1),
+                   n_k = |s|^2 +- dot (1), |a|^2 + n_k (1), scaled
+                   denominator FMA (1), exponent multiply (1), prefix add (1)
+                   = 6 full-rate, plus sqrt, reciprocal and exp2;
       inverse CDF: binary search, log2(K) compare + select pairs;
-      per step:    offset/convert/|a|^2/|a|/2a/uniform/threshold/step/cell/
-                   bounds = 22 full-rate plus one sqrt;
+      per step:    offset/convert/|a|^2/|a| scale/2a/uniform/threshold/step/
+                   cell/bounds = 22 full-rate plus one sqrt;
       Philox:      one 10-round block per 4 steps = 5 wide multiplies and
-                   10 full-rate ops per step."""
-    return (K * (5 + r["sqrt"] + r["rcp"] + r["exp2"]) + 2 * math.log2(K) + 22 + r["sqrt"]
-            + 10 + 5 * r["mul64"])
+                   10 full-rate ops per step.
+    Transcendentals issue in one slot and then occupy their own pipe for
+    r[kind] slots (the mixed probe -- one exp2 with four full-rate ops costs
+    about five slots, not 3 + 4 -- shows the overlap), so the time is
+    max(issue slots, transcendental pipe)."""
+    trans = K * 3 + 1
+    issue = K * 6 + 2 * math.log2(K) + 22 + 10 + trans + 5 * r["mul64"]
+    pipe = K * (r["sqrt"] + r["rcp"] + r["exp2"]) + r["sqrt"]
+    return max(issue, pipe)
 
 
 def measure_rates(capred, torch) -> dict:
@@ -60,7 +68,7 @@ def measure_rates(capred, torch) -> dict:
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     out = {}
     iters = 4096
-    for kind in ("fma", "exp2", "sqrt", "rcp", "mul64"):
+    for kind in ("fma", "exp2", "sqrt", "rcp", "mul64", "mix"):
         capred.probe(kind, 64, blocks, sink)
         e0.record()
         capred.probe(kind, iters, blocks, sink)

@@ -269,7 +269,8 @@ cap_status cap_plan_run_plain(cap_plan* plan, uint64_t seed, uint32_t cycle, voi
  * Measurement probes for the roofline of the rollout (not part of the method):
  * cap_probe runs `blocks` x 256 threads, each issuing 8 independent chains of
  * `iters` operations of one kind: 0 FP32 FMA, 1 exp2, 2 sqrt, 3 reciprocal,
- * 4 32x32->64-bit multiply (the Philox round product), 5 LDS atomic add.
+ * 4 32x32->64-bit multiply (the Philox round product), 5 LDS atomic add,
+ * 6 one exp2 with one multiply and three FMA (mixed issue).
  * Time it with events on `stream`; sink_dev is a [blocks] FP32 buffer that is
  * written only to keep the chains alive.  cap_copy is a plain device copy of
  * `bytes` (16-byte aligned), used to calibrate hardware byte counters. */

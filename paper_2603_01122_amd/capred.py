@@ -249,7 +249,7 @@ def philox_blocks(n: int, c0: int, c1: int, c2: int, c3: int, seed: int, device=
     return out
 
 
-PROBE_KINDS = {"fma": 0, "exp2": 1, "sqrt": 2, "rcp": 3, "mul64": 4, "lds_atomic": 5}
+PROBE_KINDS = {"fma": 0, "exp2": 1, "sqrt": 2, "rcp": 3, "mul64": 4, "lds_atomic": 5, "mix": 6}
 
 
 def probe(kind: str, iters: int, blocks: int, sink: torch.Tensor, stream=None):

@@ -91,15 +91,17 @@ __device__ void belief_update_block(const BeliefModel& m, const float* __restric
   double acc[kPerThread];
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) acc[r] = 0.0;
-  float terms[CAP_MAX_B];
   for (int t0 = 0; t0 < n_obs; t0 += kBeliefChunk) {
     const int nt = min(kBeliefChunk, n_obs - t0);
-    for (int item = tid; item < nt * G; item += nthr) {
-      const int tl = item / G, g = item - tl * G, t = t0 + tl;
+    // one thread per (transition, goal, beta): the K distances of (t, g) are
+    // recomputed per beta so that the B log-sum-exps run in parallel
+    for (int item = tid; item < nt * J; item += nthr) {
+      const int tl = item / J, j = item - tl * J, g = j / B, b = j - g * B, t = t0 + tl;
       const float zx = obs[2 * t], zy = obs[2 * t + 1];
       const int ks = recover_heading(m, obs[2 * t + 2] - zx, obs[2 * t + 3] - zy);
-      policy_terms(m, zx, zy, ks, m.gx[g], m.gy[g], m.beta, B, terms);
-      for (int b = 0; b < B; ++b) sh.ell[(tl * G + g) * B + b] = terms[b];
+      float term;
+      policy_terms(m, zx, zy, ks, m.gx[g], m.gy[g], m.beta + b, 1, &term);
+      sh.ell[tl * J + j] = term;
     }
     __syncthreads();
 #pragma unroll

@@ -166,8 +166,16 @@ __device__ __forceinline__ int cdf_index(const float* C, float thr, int Krt) {
 // |.| (a free source modifier) against rounding below zero at the goal.
 // Weights w_k = exp2(exponent) (optionally shifted by the largest exponent),
 // prefix sums C_k, heading = cdf_index(C, u C_{K-1}).
-template <int KT>
-__device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float u, bool shift,
+//
+// For KT > 0 the step table is point-symmetric (s_{k+KT/2} = -s_k, checked on
+// the host), so one dot product 2 a.s_k serves both opposite headings:
+// n_{k} = |s_k|^2 + 2 a.s_k and n_{k+KT/2} = |s_k|^2 - 2 a.s_k.  KT == 0 is the
+// general table with a run-time K.
+//
+// SHIFT (a compile-time variant, used when beta * step is large enough for
+// exp2 to overflow) subtracts the largest exponent before exponentiating.
+template <int KT, bool SHIFT>
+__device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float u,
                                             const HeadingTable& T, int Krt) {
   constexpr int KM = KT > 0 ? KT : CAP_MAX_K;
   const int K = KT > 0 ? KT : Krt;
@@ -177,33 +185,48 @@ __device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float 
   const float ax2 = ax + ax, ay2 = ay + ay;
   float C[KM];
   float acc = 0.f;
-  if (!shift) {
+  if constexpr (KT > 0) {
+    constexpr int KH = KT / 2;
+    // exponents of both halves, then the prefix sum in heading order
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-      if (KT == 0 && k >= K) break;
-      const float n = fmaf(ax2, T.fx[k], fmaf(ay2, T.fy[k], T.s2[k]));
-      const float d = fast_sqrt(fabsf(D2 + n));
-      acc += fast_exp2(n * fast_rcp(fmaf(d, ib, Dib)));
+    for (int k = 0; k < KH; ++k) {
+      const float dot = fmaf(ax2, T.fx[k], ay2 * T.fy[k]);
+      const float np = T.s2[k] + dot, nm = T.s2[k] - dot;
+      const float dp = fast_sqrt(fabsf(D2 + np)), dm = fast_sqrt(fabsf(D2 + nm));
+      C[k] = np * fast_rcp(fmaf(dp, ib, Dib));
+      C[k + KH] = nm * fast_rcp(fmaf(dm, ib, Dib));
+    }
+    if constexpr (SHIFT) {
+      float m = C[0];
+#pragma unroll
+      for (int k = 1; k < KT; ++k) m = fmaxf(m, C[k]);
+#pragma unroll
+      for (int k = 0; k < KT; ++k) C[k] -= m;
+    }
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      acc += fast_exp2(C[k]);
       C[k] = acc;
     }
+    return cdf_index<KT>(C, u * acc, Krt);
   } else {
     float m = -INFINITY;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-      if (KT == 0 && k >= K) break;
+      if (k >= K) break;
       const float n = fmaf(ax2, T.fx[k], fmaf(ay2, T.fy[k], T.s2[k]));
       const float d = fast_sqrt(fabsf(D2 + n));
       C[k] = n * fast_rcp(fmaf(d, ib, Dib));
-      m = fmaxf(m, C[k]);
+      if constexpr (SHIFT) m = fmaxf(m, C[k]);
     }
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-      if (KT == 0 && k >= K) break;
-      acc += fast_exp2(C[k] - m);
+      if (k >= K) break;
+      acc += fast_exp2(SHIFT ? C[k] - m : C[k]);
       C[k] = acc;
     }
+    return cdf_index<KT>(C, u * acc, Krt);
   }
-  return cdf_index<KT>(C, u * acc, Krt);
 }
 
 }  // namespace capred

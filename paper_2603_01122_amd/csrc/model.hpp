@@ -105,6 +105,9 @@ inline cap_status make_rollout_desc(int K, double speed, double dt, int B, const
     return fail(CAP_E_INVALID, "step v*dt is shorter than 2 lattice units (cell/2^15)");
   d.Rx = rx;
   d.Ry = ry;
+  d.sym = (K % 2 == 0) ? 1 : 0;
+  for (int k = 0; k < K / 2 && d.sym; ++k)
+    if (d.Sx[k + K / 2] != -d.Sx[k] || d.Sy[k + K / 2] != -d.Sy[k]) d.sym = 0;
   // reach check: start +- H steps must stay within int32 (checked again per start)
   const double reach = (double)H * (double)std::max(rx, ry);
   if (reach + (double)grid.nx * kLatticeScale > 2.0e9 || reach + (double)grid.ny * kLatticeScale > 2.0e9)

@@ -21,6 +21,7 @@ namespace capred {
 
 constexpr int kMaxObs = 8;
 constexpr int kXcds = 8;
+constexpr int kChunk = 8192;  // grid cells per clear/normalise chunk
 
 struct SlotDev {
   RolloutDesc rd;          // rollout of this cycle (start, ring-entry outputs)
@@ -37,6 +38,7 @@ struct CycleHeader {
   uint32_t seed_lo, seed_hi, cycle;
   int32_t n_active, n_tiles, per_tile;
   int32_t tile_begin[CAP_MAX_SLOTS + 1];
+  int32_t chunk_begin[CAP_MAX_SLOTS + 1];  // prefix of grid chunks (kChunk cells)
 };
 
 __device__ __forceinline__ const SlotDev* slots_of(const uint8_t* base) {
@@ -60,6 +62,19 @@ __global__ void __launch_bounds__(kBeliefThreads)
                       sh);
 }
 
+// Grid-sized work (clear, normalise) is cut into chunks of kChunk cells; the
+// chunks of all active humans form one index space (chunk_begin prefix) so
+// that every block streams full chunks whatever the mix of grid sizes.
+__device__ __forceinline__ int slot_of_chunk(const CycleHeader* H, int c) {
+  int lo = 0, hi = H->n_active;  // largest s with chunk_begin[s] <= c
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (H->chunk_begin[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Clears the counts (and off-grid counters) of every active slot -- or of one
 // -- and resets the tile queues for the rollout that follows.
 __global__ void __launch_bounds__(256)
@@ -67,18 +82,25 @@ __global__ void __launch_bounds__(256)
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
   if (blockIdx.x == 0 && threadIdx.x < kXcds) queues[threadIdx.x] = 0u;
   const SlotDev* sl = slots_of(base);
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int s0 = only >= 0 ? only : 0, s1 = only >= 0 ? only + 1 : H->n_active;
-  for (int s = s0; s < s1 && s < H->n_active; ++s) {
+  const int na = H->n_active;
+  const int c0 = only >= 0 ? (only < na ? H->chunk_begin[only] : 0) : 0;
+  const int c1 = only >= 0 ? (only < na ? H->chunk_begin[only + 1] : 0) : H->chunk_begin[na];
+  for (int c = c0 + (int)blockIdx.x; c < c1; c += (int)gridDim.x) {
+    const int s = __builtin_amdgcn_readfirstlane(slot_of_chunk(H, c));
     uint32_t* p = sl[s].rd.counts;
-    const size_t n = (size_t)sl[s].n_cells;
-    uint4* p4 = reinterpret_cast<uint4*>(p);
-    const size_t n4 = (reinterpret_cast<uintptr_t>(p) & 15u) ? 0 : n / 4;
-    for (size_t v = i0; v < n4; v += stride) p4[v] = make_uint4(0u, 0u, 0u, 0u);
-    for (size_t v = n4 * 4 + i0; v < n; v += stride) p[v] = 0u;
-    if (sl[s].rd.offgrid)
-      for (size_t v = i0; v < (size_t)sl[s].rd.H; v += stride) sl[s].rd.offgrid[v] = 0u;
+    const int64_t n = sl[s].n_cells;
+    const int64_t off = (int64_t)(c - H->chunk_begin[s]) * kChunk;
+    const int64_t end = min(off + (int64_t)kChunk, n);
+    if (((reinterpret_cast<uintptr_t>(p + off)) & 15u) == 0) {
+      uint4* p4 = reinterpret_cast<uint4*>(p + off);
+      const int64_t n4 = (end - off) / 4;
+      for (int64_t v = threadIdx.x; v < n4; v += blockDim.x) p4[v] = make_uint4(0u, 0u, 0u, 0u);
+      for (int64_t v = off + n4 * 4 + threadIdx.x; v < end; v += blockDim.x) p[v] = 0u;
+    } else {
+      for (int64_t v = off + threadIdx.x; v < end; v += blockDim.x) p[v] = 0u;
+    }
+    if (off == 0 && sl[s].rd.offgrid)
+      for (int v = threadIdx.x; v < sl[s].rd.H; v += blockDim.x) sl[s].rd.offgrid[v] = 0u;
   }
 }
 
@@ -86,24 +108,38 @@ __global__ void __launch_bounds__(256)
     plan_normalize_kernel(const uint8_t* __restrict__ base, int only) {
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
   const SlotDev* sl = slots_of(base);
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int s0 = only >= 0 ? only : 0, s1 = only >= 0 ? only + 1 : H->n_active;
-  for (int s = s0; s < s1 && s < H->n_active; ++s) {
+  const int na = H->n_active;
+  const int c0 = only >= 0 ? (only < na ? H->chunk_begin[only] : 0) : 0;
+  const int c1 = only >= 0 ? (only < na ? H->chunk_begin[only + 1] : 0) : H->chunk_begin[na];
+  for (int c = c0 + (int)blockIdx.x; c < c1; c += (int)gridDim.x) {
+    const int s = __builtin_amdgcn_readfirstlane(slot_of_chunk(H, c));
     float* p = sl[s].probs;
     if (!p) continue;
-    const uint32_t* c = sl[s].rd.counts;
+    const uint32_t* q = sl[s].rd.counts;
     const float N = (float)sl[s].rd.N;
-    const size_t n = (size_t)sl[s].n_cells;
-    const bool al = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(p)) & 15u) == 0;
-    const size_t n4 = al ? n / 4 : 0;
-    const uint4* c4 = reinterpret_cast<const uint4*>(c);
-    float4* p4 = reinterpret_cast<float4*>(p);
-    for (size_t v = i0; v < n4; v += stride) {
-      const uint4 x = c4[v];
-      p4[v] = make_float4((float)x.x / N, (float)x.y / N, (float)x.z / N, (float)x.w / N);
+    const int64_t n = sl[s].n_cells;
+    const int64_t off = (int64_t)(c - H->chunk_begin[s]) * kChunk;
+    const int64_t end = min(off + (int64_t)kChunk, n);
+    if (((reinterpret_cast<uintptr_t>(q + off) | reinterpret_cast<uintptr_t>(p + off)) & 15u) == 0) {
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      typedef float f32x4 __attribute__((ext_vector_type(4)));
+      const u32x4* q4 = reinterpret_cast<const u32x4*>(q + off);
+      f32x4* p4 = reinterpret_cast<f32x4*>(p + off);
+      const int64_t n4 = (end - off) / 4;
+      for (int64_t v = threadIdx.x; v < n4; v += blockDim.x) {
+        const u32x4 x = __builtin_nontemporal_load(q4 + v);
+        f32x4 y;
+        y.x = (float)x.x / N;
+        y.y = (float)x.y / N;
+        y.z = (float)x.z / N;
+        y.w = (float)x.w / N;
+        __builtin_nontemporal_store(y, p4 + v);
+      }
+      for (int64_t v = off + n4 * 4 + threadIdx.x; v < end; v += blockDim.x)
+        p[v] = (float)q[v] / N;
+    } else {
+      for (int64_t v = off + threadIdx.x; v < end; v += blockDim.x) p[v] = (float)q[v] / N;
     }
-    for (size_t v = n4 * 4 + i0; v < n; v += stride) p[v] = (float)c[v] / N;
   }
 }
 
@@ -117,7 +153,7 @@ __device__ __forceinline__ int slot_of_tile(const CycleHeader* H, int tile) {
   return lo;
 }
 
-template <int KT, int P>
+template <int KT, int P, bool SHIFT>
 __global__ void __launch_bounds__(1024)
     plan_rollout_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int cap) {
   __shared__ TileShared sh;
@@ -148,12 +184,12 @@ __global__ void __launch_bounds__(1024)
     const int64_t first = (int64_t)(tile - H->tile_begin[s]) * H->per_tile;
     // rollout_tile starts and ends with a barrier: s_tile is not rewritten
     // before every thread has read it.
-    rollout_tile<KT, P>(sl[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap);
+    rollout_tile<KT, P, SHIFT>(sl[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap);
   }
 }
 
 // One human's tiles, one block per tile (the per-human reference launch).
-template <int KT, int P>
+template <int KT, int P, bool SHIFT>
 __global__ void __launch_bounds__(1024)
     plan_rollout_one_kernel(const uint8_t* __restrict__ base, int s, int cap) {
   __shared__ TileShared sh;
@@ -161,7 +197,7 @@ __global__ void __launch_bounds__(1024)
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
   for (int i = threadIdx.x; i < 2 * cap; i += blockDim.x) win[i] = 0u;
   const int64_t first = (int64_t)blockIdx.x * H->per_tile;
-  rollout_tile<KT, P>(slots_of(base)[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap);
+  rollout_tile<KT, P, SHIFT>(slots_of(base)[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap);
 }
 
 // ---------------------------------------------------------------- host
@@ -184,7 +220,8 @@ struct Entry {
   uint32_t* queues = nullptr;   // this entry's 8 tile counters (device)
   uint8_t* dev = nullptr;       // header + slots
   uint8_t* host = nullptr;      // pinned mirror
-  hipGraphExec_t upd = nullptr, main = nullptr;
+  hipGraphExec_t upd = nullptr;
+  hipGraphExec_t main[2] = {nullptr, nullptr};  // [shift variant]
   hipEvent_t done = nullptr;
   bool pending = false;
 };
@@ -203,8 +240,9 @@ struct cap_plan {
   int cap_words = 0;            // LDS window words per buffer
   int grid_blocks = 0;
   int per_tile = 0;
-  const void* rollout_fn = nullptr;
-  const void* rollout_one_fn = nullptr;
+  const void* rollout_fn[2] = {nullptr, nullptr};      // [shift variant]
+  const void* rollout_one_fn[2] = {nullptr, nullptr};
+  int last_variant = 0;
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_update = nullptr;
   hipStream_t last_stream = nullptr;
@@ -217,12 +255,20 @@ struct cap_plan {
 
 namespace capred {
 
+template <int KT, int P>
+static void pick_fns_p(const void** r, const void** one) {
+  r[0] = (const void*)plan_rollout_kernel<KT, P, false>;
+  r[1] = (const void*)plan_rollout_kernel<KT, P, true>;
+  one[0] = (const void*)plan_rollout_one_kernel<KT, P, false>;
+  one[1] = (const void*)plan_rollout_one_kernel<KT, P, true>;
+}
+
 template <int KT>
 static void pick_fns(int P, const void** r, const void** one) {
   switch (P) {
-    case 1: *r = (const void*)plan_rollout_kernel<KT, 1>; *one = (const void*)plan_rollout_one_kernel<KT, 1>; break;
-    case 2: *r = (const void*)plan_rollout_kernel<KT, 2>; *one = (const void*)plan_rollout_one_kernel<KT, 2>; break;
-    default: *r = (const void*)plan_rollout_kernel<KT, 4>; *one = (const void*)plan_rollout_one_kernel<KT, 4>; break;
+    case 1: pick_fns_p<KT, 1>(r, one); break;
+    case 2: pick_fns_p<KT, 2>(r, one); break;
+    default: pick_fns_p<KT, 4>(r, one); break;
   }
 }
 
@@ -240,11 +286,11 @@ static size_t header_bytes(int n_active) {
   return sizeof(CycleHeader) + (size_t)n_active * sizeof(SlotDev);
 }
 
-static cap_status launch_rollout(cap_plan* p, const Entry& e, hipStream_t s) {
+static cap_status launch_rollout(cap_plan* p, const Entry& e, int variant, hipStream_t s) {
   const uint8_t* base = e.dev;
   uint32_t* q = e.queues;
   void* args[] = {(void*)&base, (void*)&q, (void*)&p->cap_words};
-  CAP_HIP(hipLaunchKernel(p->rollout_fn, dim3(p->grid_blocks), dim3(p->cfg.block_threads), args,
+  CAP_HIP(hipLaunchKernel(p->rollout_fn[variant], dim3(p->grid_blocks), dim3(p->cfg.block_threads), args,
                           (size_t)2 * p->cap_words * sizeof(uint32_t), s));
   return CAP_OK;
 }
@@ -260,18 +306,20 @@ static cap_status record_graphs(cap_plan* p, Entry& e) {
   CAP_HIP(hipStreamEndCapture(s, &g));
   CAP_HIP(hipGraphInstantiate(&e.upd, g, nullptr, nullptr, 0));
   CAP_HIP(hipGraphDestroy(g));
-  // clear -> persistent rollout -> normalise
-  CAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  hipLaunchKernelGGL(plan_zero_kernel, dim3(2048), dim3(256), 0, s, (const uint8_t*)e.dev,
-                     e.queues, minus1);
-  cap_status st = launch_rollout(p, e, s);
-  hipLaunchKernelGGL(plan_normalize_kernel, dim3(4096), dim3(256), 0, s, (const uint8_t*)e.dev,
-                     minus1);
-  hipError_t err = hipStreamEndCapture(s, &g);
-  if (st != CAP_OK) return st;
-  if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
-  CAP_HIP(hipGraphInstantiate(&e.main, g, nullptr, nullptr, 0));
-  CAP_HIP(hipGraphDestroy(g));
+  // clear -> persistent rollout -> normalise, once per rollout variant
+  for (int v = 0; v < 2; ++v) {
+    CAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(plan_zero_kernel, dim3(2048), dim3(256), 0, s, (const uint8_t*)e.dev,
+                       e.queues, minus1);
+    cap_status st = launch_rollout(p, e, v, s);
+    hipLaunchKernelGGL(plan_normalize_kernel, dim3(4096), dim3(256), 0, s, (const uint8_t*)e.dev,
+                       minus1);
+    hipError_t err = hipStreamEndCapture(s, &g);
+    if (st != CAP_OK) return st;
+    if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
+    CAP_HIP(hipGraphInstantiate(&e.main[v], g, nullptr, nullptr, 0));
+    CAP_HIP(hipGraphDestroy(g));
+  }
   return CAP_OK;
 }
 
@@ -279,7 +327,8 @@ static void destroy_plan(cap_plan* p) {
   if (!p) return;
   for (auto& e : p->ring) {
     if (e.upd) (void)hipGraphExecDestroy(e.upd);
-    if (e.main) (void)hipGraphExecDestroy(e.main);
+    for (int v = 0; v < 2; ++v)
+      if (e.main[v]) (void)hipGraphExecDestroy(e.main[v]);
     if (e.done) (void)hipEventDestroy(e.done);
     if (e.dev) (void)hipFree(e.dev);
     if (e.host) (void)hipHostFree(e.host);
@@ -299,7 +348,7 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
   H->seed_hi = (uint32_t)(seed >> 32);
   H->cycle = cycle;
   H->per_tile = p->per_tile;
-  int n = 0, tiles = 0;
+  int n = 0, tiles = 0, chunks = 0, variant = 0;
   int64_t parts = 0, steps = 0;
   for (auto& hs : p->slots) {
     if (!hs.active) continue;
@@ -314,6 +363,7 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
     sd.rd.belief = hs.belief + (size_t)re * sd.bm.G * sd.bm.B;
     sd.n_cells = hs.n_cells;
     sd.reset = hs.reset ? 1 : 0;
+    variant |= sd.rd.shift ? 1 : 0;
     hs.reset = false;
     sd.n_obs = hs.n_staged;
     sd.obs[0] = hs.last[0];
@@ -328,13 +378,17 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
     sd.rd.X0 = (int32_t)lattice_coord((double)hs.last[0], hs.grid.x0, hs.grid.cell);
     sd.rd.Y0 = (int32_t)lattice_coord((double)hs.last[1], hs.grid.y0, hs.grid.cell);
     H->tile_begin[n] = tiles;
+    H->chunk_begin[n] = chunks;
     tiles += (int)((sd.rd.N + p->per_tile - 1) / p->per_tile);
+    chunks += (int)((hs.n_cells + kChunk - 1) / kChunk);
     parts += sd.rd.N;
     steps += (int64_t)sd.rd.N * sd.rd.H;
     ++n;
   }
   H->tile_begin[n] = tiles;
+  H->chunk_begin[n] = chunks;
   H->n_active = n;
+  p->last_variant = variant;
   H->n_tiles = tiles;
   p->particles = parts;
   p->psteps = steps;
@@ -382,7 +436,7 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
   if (cfg.particles_per_thread != 1 && cfg.particles_per_thread != 2 &&
       cfg.particles_per_thread != 4)
     return fail(CAP_E_INVALID, "particles_per_thread must be 1, 2 or 4");
-  if (cfg.lds_bytes == 0) cfg.lds_bytes = 75 * 1024;
+  if (cfg.lds_bytes == 0) cfg.lds_bytes = 40 * 1024;
   if (cfg.lds_bytes < 2048 || cfg.lds_bytes > 144 * 1024)
     return fail(CAP_E_INVALID, "lds_bytes must be in [2 KiB, 144 KiB]");
   cap_plan* p = new cap_plan();
@@ -391,13 +445,20 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
   p->ring.resize(cfg.ring);
   p->per_tile = cfg.block_threads * cfg.particles_per_thread;
   p->cap_words = cfg.lds_bytes / (2 * (int)sizeof(uint32_t));
-  select_kernels(cfg.K, cfg.particles_per_thread, &p->rollout_fn, &p->rollout_one_fn);
+  select_kernels(cfg.K, cfg.particles_per_thread, p->rollout_fn, p->rollout_one_fn);
   const size_t dyn = (size_t)2 * p->cap_words * sizeof(uint32_t);
-  hipError_t e = hipFuncSetAttribute(p->rollout_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)dyn);
-  (void)e;  // not required on gfx950; the occupancy query below validates the size
-  int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p->rollout_fn, cfg.block_threads, dyn);
+  hipError_t e = hipSuccess;
+  for (int v = 0; v < 2; ++v) {
+    e = hipFuncSetAttribute(p->rollout_fn[v], hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    (void)e;  // not required on gfx950; the occupancy query below validates the size
+  }
+  // both variants share the persistent grid: size it for the tighter one
+  int per_cu = 1 << 30;
+  for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+    int pc = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, p->rollout_fn[v], cfg.block_threads, dyn);
+    per_cu = std::min(per_cu, pc);
+  }
   if (e != hipSuccess || per_cu < 1) {
     destroy_plan(p);
     return e != hipSuccess ? hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor")
@@ -465,6 +526,8 @@ extern "C" cap_status cap_plan_set_slot(cap_plan* p, int32_t slot, const cap_slo
                          &ns.tmpl.rd);
   if (st != CAP_OK) return st;
   ns.grid = d->grid;
+  if ((m.K == 4 || m.K == 8 || m.K == 16 || m.K == 32) && !ns.tmpl.rd.sym)
+    return fail(CAP_E_UNSUPPORTED, "the lattice step table of this grid is not point-symmetric");
   if ((st = check_position(ns, d->last_xy[0], d->last_xy[1], d->H,
                            std::max(ns.tmpl.rd.Rx, ns.tmpl.rd.Ry))) != CAP_OK)
     return st;
@@ -535,7 +598,7 @@ extern "C" cap_status cap_plan_run(cap_plan* p, uint64_t seed, uint32_t cycle, v
   Entry& en = p->ring[e];
   CAP_HIP(hipGraphLaunch(en.upd, s));
   CAP_HIP(hipEventRecord(p->ev_update, s));
-  CAP_HIP(hipGraphLaunch(en.main, s));
+  CAP_HIP(hipGraphLaunch(en.main[p->last_variant], s));
   CAP_HIP(hipEventRecord(en.done, s));
   en.pending = true;
   p->last_stream = s;
@@ -559,15 +622,15 @@ extern "C" cap_status cap_plan_run_plain(cap_plan* p, uint64_t seed, uint32_t cy
     hipLaunchKernelGGL(plan_update_kernel, dim3(1), dim3(kBeliefThreads), 0, s, base, i);
     if (i == H->n_active - 1) CAP_HIP(hipEventRecord(p->ev_update, s));
     const size_t n = (size_t)sl[i].n_cells;
-    const unsigned zb = (unsigned)std::min<size_t>((n / 4 + 255) / 256 + 1, 2048);
+    const unsigned zb = (unsigned)std::min<size_t>((n + kChunk - 1) / kChunk, 2048);
     hipLaunchKernelGGL(plan_zero_kernel, dim3(zb), dim3(256), 0, s, base, en.queues, i);
     const int tiles = H->tile_begin[i + 1] - H->tile_begin[i];
     int si = i;
     void* args[] = {(void*)&base, (void*)&si, (void*)&p->cap_words};
-    CAP_HIP(hipLaunchKernel(p->rollout_one_fn, dim3(tiles), dim3(p->cfg.block_threads), args,
+    CAP_HIP(hipLaunchKernel(p->rollout_one_fn[sl[i].rd.shift ? 1 : 0], dim3(tiles), dim3(p->cfg.block_threads), args,
                             (size_t)2 * p->cap_words * sizeof(uint32_t), s));
     if (sl[i].probs) {
-      const unsigned nb = (unsigned)std::min<size_t>((n / 4 + 255) / 256 + 1, 4096);
+      const unsigned nb = (unsigned)std::min<size_t>((n + kChunk - 1) / kChunk, 4096);
       hipLaunchKernelGGL(plan_normalize_kernel, dim3(nb), dim3(256), 0, s, base, i);
     }
   }
@@ -590,7 +653,7 @@ extern "C" cap_status cap_plan_replay_rollout(cap_plan* p, void* stream, void* e
   hipLaunchKernelGGL(plan_zero_kernel, dim3(2048), dim3(256), 0, s, (const uint8_t*)en.dev,
                      en.queues, minus1);
   if (ev_start) CAP_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(ev_start), s));
-  cap_status st = launch_rollout(p, en, s);
+  cap_status st = launch_rollout(p, en, p->last_variant, s);
   if (st != CAP_OK) return st;
   if (ev_end) CAP_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(ev_end), s));
   CAP_HIP(hipGetLastError());

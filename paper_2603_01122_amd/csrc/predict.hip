@@ -9,7 +9,7 @@ namespace capred {
 // LDS budget of the histogram windows of the single-human kernel (two
 // buffers: the step being binned and the step being flushed).
 constexpr int kPlainThreads = 256;
-constexpr int kPlainLdsBytes = 64 * 1024;
+constexpr int kPlainLdsBytes = 40 * 1024;
 
 __global__ void __launch_bounds__(256) zero_u32_kernel(uint32_t* __restrict__ p, size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) normalize_kernel(const uint32_t* __restri
   for (size_t v = head * 4 + i; v < n; v += stride) p[v] = (float)c[v] / N;
 }
 
-template <int KT, int P>
+template <int KT, int P, bool SHIFT>
 __global__ void __launch_bounds__(kPlainThreads)
     rollout_plain_kernel(const RolloutDesc d, uint32_t seed_lo, uint32_t seed_hi, int cap) {
   __shared__ TileShared sh;
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kPlainThreads)
   for (int i = threadIdx.x; i < 2 * cap; i += blockDim.x) win[i] = 0u;
   // the first barrier inside rollout_tile orders this clear before any binning
   const int64_t first = (int64_t)blockIdx.x * P * blockDim.x;
-  rollout_tile<KT, P>(d, first, seed_lo, seed_hi, sh, win, cap);
+  rollout_tile<KT, P, SHIFT>(d, first, seed_lo, seed_hi, sh, win, cap);
 }
 
 // Track simulator: one thread per track, the same heading draw as the rollout
@@ -65,8 +65,7 @@ __global__ void __launch_bounds__(256)
   const int32_t GX = (int32_t)rint(((double)goal[2 * r] - x0) / q);
   const int32_t GY = (int32_t)rint(((double)goal[2 * r + 1] - y0) / q);
   const float ib = (float)(1.0 / (-(double)beta[r] * q * (double)kLog2e));
-  const bool shift = (double)beta[r] * (double)d.Rx * q > kNoShiftLimit ||
-                     (double)beta[r] * (double)d.Ry * q > kNoShiftLimit || d.shift;
+  const bool shift = (double)beta[r] * (double)max(d.Rx, d.Ry) * q > kNoShiftLimit;
   uint4 w = make_uint4(0u, 0u, 0u, 0u);
   for (int t = 0; t <= T; ++t) {
     if (t > 0) {
@@ -74,7 +73,9 @@ __global__ void __launch_bounds__(256)
       if (s == 0) w = philox10((uint32_t)r, (uint32_t)((t - 1) >> 2), stream_id, 0xFFFFFFFFu,
                                seed_lo, seed_hi);
       const float u = uniform24f(pick_word(w, s));
-      const int k = draw_heading<KT>((float)(X - GX), (float)(Y - GY), ib, u, shift, d.T, d.K);
+      const int k =
+          shift ? draw_heading<KT, true>((float)(X - GX), (float)(Y - GY), ib, u, d.T, d.K)
+                : draw_heading<KT, false>((float)(X - GX), (float)(Y - GY), ib, u, d.T, d.K);
       X += d.Sx[k];
       Y += d.Sy[k];
     }
@@ -111,15 +112,20 @@ static cap_status launch_plain_t(const RolloutDesc& d, uint32_t slo, uint32_t sh
   const int64_t per_block = (int64_t)P * kPlainThreads;
   const int64_t blocks = (d.N + per_block - 1) / per_block;
   const size_t lds = (size_t)2 * cap * sizeof(uint32_t);
-  hipLaunchKernelGGL((rollout_plain_kernel<KT, P>), dim3((unsigned)blocks), dim3(kPlainThreads),
-                     lds, s, d, slo, shi, cap);
+  if (d.shift)
+    hipLaunchKernelGGL((rollout_plain_kernel<KT, P, true>), dim3((unsigned)blocks),
+                       dim3(kPlainThreads), lds, s, d, slo, shi, cap);
+  else
+    hipLaunchKernelGGL((rollout_plain_kernel<KT, P, false>), dim3((unsigned)blocks),
+                       dim3(kPlainThreads), lds, s, d, slo, shi, cap);
   CAP_HIP(hipGetLastError());
   return CAP_OK;
 }
 
 static cap_status launch_plain(const RolloutDesc& d, uint32_t slo, uint32_t shi, hipStream_t s) {
   const int cap = kPlainLdsBytes / (2 * (int)sizeof(uint32_t));
-  switch (d.K) {
+  // specialised kernels assume a point-symmetric step table
+  switch (d.sym ? d.K : 0) {
     case 4: return launch_plain_t<4, 1>(d, slo, shi, cap, s);
     case 8: return launch_plain_t<8, 1>(d, slo, shi, cap, s);
     case 16: return launch_plain_t<16, 1>(d, slo, shi, cap, s);
@@ -201,7 +207,7 @@ extern "C" cap_status cap_simulate_tracks(int32_t K, double speed, double dt, do
 #define CAP_SIM(KT)                                                                          \
   hipLaunchKernelGGL((simulate_kernel<KT>), grid_dim, blk, 0, s, d, n, T, start_dev, beta_dev, \
                      goal_dev, x0, y0, cell, stream_id, slo, shi, lat_dev, pos_dev)
-  switch (K) {
+  switch (d.sym ? K : 0) {
     case 4: CAP_SIM(4); break;
     case 8: CAP_SIM(8); break;
     case 16: CAP_SIM(16); break;

@@ -13,11 +13,12 @@ constexpr int kProbeChains = 8;
 template <int KIND>
 __global__ void __launch_bounds__(256) probe_kernel(int64_t iters, float seed,
                                                     float* __restrict__ sink) {
-  float x[kProbeChains];
+  float x[kProbeChains], y[kProbeChains];
   uint32_t u[kProbeChains];
 #pragma unroll
   for (int c = 0; c < kProbeChains; ++c) {
     x[c] = seed + 0.001f * (float)(threadIdx.x + 7 * c);
+    y[c] = x[c] * 0.5f;
     u[c] = threadIdx.x * 2654435761u + c;
   }
   __shared__ uint32_t lds[4096];
@@ -36,12 +37,18 @@ __global__ void __launch_bounds__(256) probe_kernel(int64_t iters, float seed,
         const uint64_t p = (uint64_t)u[c] * 0xD2511F53u;
         u[c] = (uint32_t)(p >> 32) ^ (uint32_t)p;
       }
+      if (KIND == 6) {
+        x[c] = fast_exp2(x[c] * -0.5f);
+        y[c] = fmaf(y[c], 0.999f, 1e-4f);
+        y[c] = fmaf(y[c], 0.999f, 1e-4f);
+        y[c] = fmaf(y[c], 0.999f, 1e-4f);
+      }
       if (KIND == 5) atomicAdd(&lds[(u[c] + (uint32_t)i * 97u + c * 509u) & 4095u], 1u);
     }
   }
   float acc = 0.f;
 #pragma unroll
-  for (int c = 0; c < kProbeChains; ++c) acc += x[c] + (float)u[c];
+  for (int c = 0; c < kProbeChains; ++c) acc += x[c] + y[c] + (float)u[c];
   if (KIND == 5) {
     __syncthreads();
     acc += (float)lds[threadIdx.x];
@@ -61,7 +68,7 @@ using namespace capred;
 
 extern "C" cap_status cap_probe(int32_t kind, int64_t iters, int32_t blocks, float* sink_dev,
                                 void* stream) {
-  if (kind < 0 || kind > 5 || iters < 1 || blocks < 1 || !sink_dev)
+  if (kind < 0 || kind > 6 || iters < 1 || blocks < 1 || !sink_dev)
     return fail(CAP_E_INVALID, "probe: kind in [0,5], iters >= 1, blocks >= 1, sink required");
   hipStream_t s = as_stream(stream);
   const dim3 g((unsigned)blocks), b(256);
@@ -71,7 +78,8 @@ extern "C" cap_status cap_probe(int32_t kind, int64_t iters, int32_t blocks, flo
     case 2: hipLaunchKernelGGL(probe_kernel<2>, g, b, 0, s, iters, 0.5f, sink_dev); break;
     case 3: hipLaunchKernelGGL(probe_kernel<3>, g, b, 0, s, iters, 0.5f, sink_dev); break;
     case 4: hipLaunchKernelGGL(probe_kernel<4>, g, b, 0, s, iters, 0.5f, sink_dev); break;
-    default: hipLaunchKernelGGL(probe_kernel<5>, g, b, 0, s, iters, 0.5f, sink_dev); break;
+    case 5: hipLaunchKernelGGL(probe_kernel<5>, g, b, 0, s, iters, 0.5f, sink_dev); break;
+    default: hipLaunchKernelGGL(probe_kernel<6>, g, b, 0, s, iters, 0.5f, sink_dev); break;
   }
   CAP_HIP(hipGetLastError());
   return CAP_OK;

@@ -16,6 +16,7 @@ struct RolloutDesc {
   int32_t Rx, Ry;           // max |S_kx|, |S_ky|: reach per step, lattice units
   uint32_t human, cycle;
   int32_t shift;            // 1: subtract the largest exponent (large beta * step)
+  int32_t sym;              // 1: S_{k+K/2} = -S_k for every k < K/2 (K even)
   HeadingTable T;           // lattice-unit steps and squared lengths (FP32)
   int32_t Sx[CAP_MAX_K], Sy[CAP_MAX_K];
   float ibeta[CAP_MAX_B];   // 1 / (-beta q log2(e)), q = lattice pitch
@@ -66,8 +67,9 @@ __device__ __forceinline__ uint32_t pick_word(const uint4& w, int s) {
 }
 
 // Processes particles [first, first + P * blockDim.x) of human d (clipped to N).
-// win: 2 * cap words of LDS, zero on entry and on exit.
-template <int KT, int P>
+// win: 2 * cap words of LDS (each word two 16-bit cell counters), zero on
+// entry and on exit.
+template <int KT, int P, bool SHIFT>
 __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_lo,
                              uint32_t seed_hi, TileShared& sh, uint32_t* win, int cap) {
   const int tid = threadIdx.x;
@@ -125,7 +127,6 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     }
   }
 
-  const bool shift = d.shift != 0;
   const size_t plane = (size_t)d.nx * (size_t)d.ny;
   uint4 rw[P];
   const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
@@ -138,26 +139,31 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
                          seed_hi);
     }
     const Window wd = step_window(d, t);
-    const bool lds_mode = wd.w * wd.h <= cap;
+    // two 16-bit counters per LDS word (a tile never holds 65536 particles);
+    // rows padded to an even number of cells
+    const int half_w = (wd.w + 1) >> 1;
+    const bool lds_mode = half_w * wd.h <= cap;
     uint32_t* buf = win + (t & 1) * cap;
     uint32_t* grid_t = d.counts + (size_t)(t - 1) * plane;
     bool off_any = false;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       bool off = false;
+      // computed for inactive lanes too (harmless state), so that the P
+      // particles stay in one basic block; only emplacement is predicated
+      const float u = uniform24f(pick_word(rw[p], s));
+      const int k = draw_heading<KT, SHIFT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p],
+                                            u, d.T, d.K);
+      const int2 st = sh.S[k];
+      X[p] += st.x;
+      Y[p] += st.y;
       if (act[p]) {
-        const float u = uniform24f(pick_word(rw[p], s));
-        const int k = draw_heading<KT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p], u,
-                                       shift, d.T, d.K);
-        const int2 st = sh.S[k];
-        X[p] += st.x;
-        Y[p] += st.y;
         if (d.trace_k) d.trace_k[(size_t)idx[p] * d.H + (t - 1)] = (uint8_t)k;
         const int cx = X[p] >> kLatticeShift, cy = Y[p] >> kLatticeShift;
         if ((unsigned)cx < (unsigned)d.nx && (unsigned)cy < (unsigned)d.ny) {
           const unsigned lx = (unsigned)(cx - wd.x0), ly = (unsigned)(cy - wd.y0);
           if (lds_mode && lx < (unsigned)wd.w && ly < (unsigned)wd.h)
-            atomicAdd(buf + ly * wd.w + lx, 1u);
+            atomicAdd(buf + ly * half_w + (lx >> 1), 1u << ((lx & 1u) << 4));
           else
             atomicAdd(grid_t + (size_t)cy * d.nx + cx, 1u);
         } else {
@@ -173,12 +179,14 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     // ---- flush the window of step t (coalesced along rows), clear it
     if (lds_mode) {
       for (int r = wave; r < wd.h; r += nwaves) {
-        uint32_t* row = buf + r * wd.w;
+        uint32_t* row = buf + r * half_w;
         uint32_t* grow = grid_t + (size_t)(wd.y0 + r) * d.nx + wd.x0;
-        for (int c = lane; c < wd.w; c += 64) {
+        for (int c = lane; c < half_w; c += 64) {
           const uint32_t v = row[c];
           if (v) {
-            atomicAdd(grow + c, v);
+            const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
+            if (lo) atomicAdd(grow + 2 * c, lo);
+            if (hi) atomicAdd(grow + 2 * c + 1, hi);
             row[c] = 0u;
           }
         }
