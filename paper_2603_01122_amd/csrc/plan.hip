@@ -291,7 +291,7 @@ static cap_status launch_rollout(cap_plan* p, const Entry& e, int variant, hipSt
   uint32_t* q = e.queues;
   void* args[] = {(void*)&base, (void*)&q, (void*)&p->cap_words};
   CAP_HIP(hipLaunchKernel(p->rollout_fn[variant], dim3(p->grid_blocks), dim3(p->cfg.block_threads), args,
-                          (size_t)2 * p->cap_words * sizeof(uint32_t), s));
+                          window_lds_bytes(p->cap_words, p->per_tile), s));
   return CAP_OK;
 }
 
@@ -446,7 +446,7 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
   p->per_tile = cfg.block_threads * cfg.particles_per_thread;
   p->cap_words = cfg.lds_bytes / (2 * (int)sizeof(uint32_t));
   select_kernels(cfg.K, cfg.particles_per_thread, p->rollout_fn, p->rollout_one_fn);
-  const size_t dyn = (size_t)2 * p->cap_words * sizeof(uint32_t);
+  const size_t dyn = window_lds_bytes(p->cap_words, p->per_tile);
   hipError_t e = hipSuccess;
   for (int v = 0; v < 2; ++v) {
     e = hipFuncSetAttribute(p->rollout_fn[v], hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
@@ -628,7 +628,7 @@ extern "C" cap_status cap_plan_run_plain(cap_plan* p, uint64_t seed, uint32_t cy
     int si = i;
     void* args[] = {(void*)&base, (void*)&si, (void*)&p->cap_words};
     CAP_HIP(hipLaunchKernel(p->rollout_one_fn[sl[i].rd.shift ? 1 : 0], dim3(tiles), dim3(p->cfg.block_threads), args,
-                            (size_t)2 * p->cap_words * sizeof(uint32_t), s));
+                            window_lds_bytes(p->cap_words, p->per_tile), s));
     if (sl[i].probs) {
       const unsigned nb = (unsigned)std::min<size_t>((n + kChunk - 1) / kChunk, 4096);
       hipLaunchKernelGGL(plan_normalize_kernel, dim3(nb), dim3(256), 0, s, base, i);

@@ -111,7 +111,7 @@ static cap_status launch_plain_t(const RolloutDesc& d, uint32_t slo, uint32_t sh
                                  hipStream_t s) {
   const int64_t per_block = (int64_t)P * kPlainThreads;
   const int64_t blocks = (d.N + per_block - 1) / per_block;
-  const size_t lds = (size_t)2 * cap * sizeof(uint32_t);
+  const size_t lds = window_lds_bytes(cap, P * kPlainThreads);
   if (d.shift)
     hipLaunchKernelGGL((rollout_plain_kernel<KT, P, true>), dim3((unsigned)blocks),
                        dim3(kPlainThreads), lds, s, d, slo, shi, cap);

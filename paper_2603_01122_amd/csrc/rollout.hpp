@@ -34,6 +34,7 @@ struct TileShared {
   int2 goal[CAP_MAX_G];
   float ibeta[CAP_MAX_B];
   uint32_t off[2];          // off-grid counters of the two in-flight steps
+  uint32_t ntouch[3];       // first-touched window words per step (rotating)
   int last_pos;
 };
 
@@ -66,9 +67,18 @@ __device__ __forceinline__ uint32_t pick_word(const uint4& w, int s) {
   return s == 0 ? w.x : (s == 1 ? w.y : (s == 2 ? w.z : w.w));
 }
 
+// LDS bytes of the histogram window of one block: two window buffers of
+// `cap` words (two 16-bit cell counters per word) and two lists of the words
+// first touched in a step (16-bit word indices, one per particle at most).
+__host__ __device__ constexpr size_t window_lds_bytes(int cap, int particles_per_tile) {
+  return (size_t)2 * cap * sizeof(uint32_t) + (size_t)2 * particles_per_tile * sizeof(uint16_t);
+}
+
 // Processes particles [first, first + P * blockDim.x) of human d (clipped to N).
-// win: 2 * cap words of LDS (each word two 16-bit cell counters), zero on
-// entry and on exit.
+// win: window_lds_bytes(cap, P * blockDim.x) bytes of LDS, zero on entry and
+// on exit (cap <= 65536).  A step's window is flushed from the list of words
+// its particles touched first, so the flush costs one entry per occupied
+// word, whatever the window's area.
 template <int KT, int P, bool SHIFT>
 __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_lo,
                              uint32_t seed_hi, TileShared& sh, uint32_t* win, int cap) {
@@ -88,6 +98,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     sh.last_pos = last;
     sh.off[0] = 0u;
     sh.off[1] = 0u;
+    sh.ntouch[0] = sh.ntouch[1] = sh.ntouch[2] = 0u;
   }
   for (int k = tid; k < d.K; k += nthr) sh.S[k] = make_int2(d.Sx[k], d.Sy[k]);
   for (int g = tid; g < d.G; g += nthr) sh.goal[g] = make_int2(d.GX[g], d.GY[g]);
@@ -129,8 +140,11 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
 
   const size_t plane = (size_t)d.nx * (size_t)d.ny;
   uint4 rw[P];
-  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-  for (int t = 1; t <= d.H; ++t) {
+  const int lane = tid & 63;
+  const int list_cap = P * nthr;
+  uint16_t* lists = reinterpret_cast<uint16_t*>(win + 2 * cap);
+  int m3 = 1;  // t mod 3
+  for (int t = 1; t <= d.H; ++t, m3 = (m3 == 2 ? 0 : m3 + 1)) {
     const int s = (t - 1) & 3;
     if (s == 0) {
 #pragma unroll
@@ -144,6 +158,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     const int half_w = (wd.w + 1) >> 1;
     const bool lds_mode = half_w * wd.h <= cap;
     uint32_t* buf = win + (t & 1) * cap;
+    uint16_t* list = lists + (t & 1) * list_cap;
     uint32_t* grid_t = d.counts + (size_t)(t - 1) * plane;
     bool off_any = false;
 #pragma unroll
@@ -157,18 +172,33 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
       const int2 st = sh.S[k];
       X[p] += st.x;
       Y[p] += st.y;
+      bool fresh = false;     // this lane turned an empty window word non-empty
+      uint32_t widx = 0;
       if (act[p]) {
         if (d.trace_k) d.trace_k[(size_t)idx[p] * d.H + (t - 1)] = (uint8_t)k;
         const int cx = X[p] >> kLatticeShift, cy = Y[p] >> kLatticeShift;
         if ((unsigned)cx < (unsigned)d.nx && (unsigned)cy < (unsigned)d.ny) {
           const unsigned lx = (unsigned)(cx - wd.x0), ly = (unsigned)(cy - wd.y0);
-          if (lds_mode && lx < (unsigned)wd.w && ly < (unsigned)wd.h)
-            atomicAdd(buf + ly * half_w + (lx >> 1), 1u << ((lx & 1u) << 4));
-          else
+          if (lds_mode && lx < (unsigned)wd.w && ly < (unsigned)wd.h) {
+            widx = ly * half_w + (lx >> 1);
+            fresh = atomicAdd(buf + widx, 1u << ((lx & 1u) << 4)) == 0u;
+          } else {
             atomicAdd(grid_t + (size_t)cy * d.nx + cx, 1u);
+          }
         } else {
           off = true;
         }
+      }
+      // wave-aggregated append of the freshly touched words
+      const uint64_t fm = __ballot(fresh);
+      if (fm) {
+        const int leader = __ffsll((unsigned long long)fm) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&sh.ntouch[m3], (uint32_t)__popcll(fm));
+        base = __shfl(base, leader, 64);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
+        if (fresh) list[base + below] = (uint16_t)widx;
       }
       off_any |= off;
       const uint64_t m = __ballot(off);
@@ -176,26 +206,27 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     }
     (void)off_any;
     __syncthreads();
-    // ---- flush the window of step t (coalesced along rows), clear it
+    // ---- flush the touched words of step t's window, clear them
     if (lds_mode) {
-      for (int r = wave; r < wd.h; r += nwaves) {
-        uint32_t* row = buf + r * half_w;
-        uint32_t* grow = grid_t + (size_t)(wd.y0 + r) * d.nx + wd.x0;
-        for (int c = lane; c < half_w; c += 64) {
-          const uint32_t v = row[c];
-          if (v) {
-            const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
-            if (lo) atomicAdd(grow + 2 * c, lo);
-            if (hi) atomicAdd(grow + 2 * c + 1, hi);
-            row[c] = 0u;
-          }
-        }
+      const uint32_t nt = sh.ntouch[m3];
+      for (uint32_t i = tid; i < nt; i += nthr) {
+        const uint32_t w = list[i];
+        const uint32_t v = buf[w];
+        buf[w] = 0u;
+        const uint32_t ry = w / (uint32_t)half_w, rx = 2u * (w - ry * (uint32_t)half_w);
+        uint32_t* g = grid_t + (size_t)(wd.y0 + ry) * d.nx + wd.x0 + rx;
+        const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
+        if (lo) atomicAdd(g, lo);
+        if (hi) atomicAdd(g + 1, hi);
       }
     }
     if (tid == 0) {
       const uint32_t v = sh.off[t & 1];
       if (v && d.offgrid) atomicAdd(d.offgrid + (t - 1), v);
       sh.off[t & 1] = 0u;
+      // the list counter of step t-1 was read before this step's barrier and
+      // is next appended to at step t+2, after the next barrier
+      sh.ntouch[m3 == 0 ? 2 : m3 - 1] = 0u;
     }
   }
   __syncthreads();
