@@ -109,6 +109,11 @@ def lib():
             L.orc_simulate_tracks.argtypes = [i32, d, d, d, d, d, i32, i32, _f64p, _f32p, _f32p,
                                               u64, u32, _nullable(_i64p), _nullable(_f32p)]
             L.orc_simulate_tracks.restype = i32
+            L.orc_smooth.argtypes = [_u32p, i32, i32, i32, i64, d, i32, _nullable(_i64p), i64,
+                                     _f64p, i32]
+            L.orc_smooth.restype = i32
+            L.orc_union_max.argtypes = [C.POINTER(C.POINTER(C.c_float)), i32, i64, _f32p]
+            L.orc_union_max.restype = i32
             _lib = L
     return _lib
 
@@ -287,3 +292,31 @@ def simulate_tracks(*, K, speed, dt, frame, start, beta, goal, T, seed=0, stream
                                    pos.reshape(-1))
     _check(rc, "simulate_tracks")
     return lat, pos
+
+
+# ------------------------------------------------------------ smoothing and union
+def smooth(counts: np.ndarray, N: int, sigma: float, radius: int, cells=None,
+           nthreads=None) -> np.ndarray:
+    """Gaussian-smoothed occupancy (Sec. III-B) as the direct 2-D sum in FP64.
+    counts [H, ny, nx] uint32; returns float64 [H, ny, nx], or [len(cells)]
+    for flattened (t, y, x) indices `cells`."""
+    counts = np.ascontiguousarray(counts, np.uint32)
+    H, ny, nx = counts.shape
+    idx = None if cells is None else np.ascontiguousarray(cells, np.int64).reshape(-1)
+    out = np.empty(counts.size if idx is None else idx.size, np.float64)
+    _check(lib().orc_smooth(counts.reshape(-1), H, ny, nx, N, float(sigma), int(radius), idx,
+                            0 if idx is None else idx.size, out, nthreads or default_threads()),
+           "smooth")
+    return out.reshape(counts.shape) if idx is None else out
+
+
+def union_max(grids) -> np.ndarray:
+    """Point-wise maximum over humans of equally shaped float32 grids (Sec. IV-B)."""
+    arrs = [np.ascontiguousarray(g, np.float32) for g in grids]
+    shape = arrs[0].shape
+    assert all(a.shape == shape for a in arrs)
+    ptrs = (C.POINTER(C.c_float) * len(arrs))(
+        *[a.ctypes.data_as(C.POINTER(C.c_float)) for a in arrs])
+    out = np.empty(shape, np.float32)
+    _check(lib().orc_union_max(ptrs, len(arrs), arrs[0].size, out.reshape(-1)), "union_max")
+    return out

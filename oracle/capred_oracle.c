@@ -581,3 +581,71 @@ int orc_simulate_tracks(int K, double speed, double dt, double x0, double y0, do
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Gaussian-smoothed occupancy (Sec. III-B: a Gaussian convolution of the
+ * particle batch before emplacement).  Reading: convolving the particle set
+ * with a Gaussian and emplacing equals convolving the point histogram with a
+ * discrete Gaussian kernel, so
+ *   p~_t(x, y) = (1/N) sum_{|dx|<=r, |dy|<=r} w(dx, dy) count_t(x - dx, y - dy),
+ *   w(dx, dy) = exp(-(dx^2 + dy^2) / (2 sigma^2)) / Z,  Z = sum of the numerators
+ * over the square (2r+1)^2 window, with counts outside the grid taken as zero
+ * (mass that the kernel spreads past the border is dropped, like particles
+ * that leave the grid).  sigma and r are in cells.  Written as the direct 2-D
+ * sum in FP64.  cells[0..n_cells) selects flattened (t, y, x) outputs, written
+ * to out[i]; cells == NULL computes all H*ny*nx outputs in order. */
+int orc_smooth(const uint32_t* counts, int H, int ny, int nx, int64_t N, double sigma,
+               int radius, const int64_t* cells, int64_t n_cells, double* out, int nthreads) {
+  if (H < 0 || ny < 1 || nx < 1 || N < 1 || radius < 0 || radius > 64) return -1;
+  if (radius > 0 && !(sigma > 0)) return -1;
+  const int W = 2 * radius + 1;
+  double* w = (double*)malloc(sizeof(double) * W * W);
+  if (!w) return -2;
+  double Z = 0.0;
+  for (int dy = -radius; dy <= radius; ++dy)
+    for (int dx = -radius; dx <= radius; ++dx) {
+      const double v = radius == 0 ? 1.0 : exp(-(double)(dx * dx + dy * dy) / (2.0 * sigma * sigma));
+      w[(dy + radius) * W + (dx + radius)] = v;
+      Z += v;
+    }
+  const int64_t plane = (int64_t)ny * nx;
+  const int64_t n = cells ? n_cells : (int64_t)H * plane;
+  int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1) reduction(|:bad)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t c = cells ? cells[i] : i;
+    if (c < 0 || c >= (int64_t)H * plane) { bad |= 1; continue; }
+    const int64_t t = c / plane;
+    const int y = (int)((c % plane) / nx), x = (int)(c % nx);
+    double acc = 0.0;
+    for (int dy = -radius; dy <= radius; ++dy) {
+      const int sy = y - dy;
+      if (sy < 0 || sy >= ny) continue;
+      for (int dx = -radius; dx <= radius; ++dx) {
+        const int sx = x - dx;
+        if (sx < 0 || sx >= nx) continue;
+        acc += w[(dy + radius) * W + (dx + radius)] / Z *
+               (double)counts[t * plane + (int64_t)sy * nx + sx];
+      }
+    }
+    out[i] = acc / (double)N;
+  }
+  free(w);
+  return bad ? -1 : 0;
+}
+
+/* Point-wise maximum over humans of per-step grids (Sec. IV-B: the union of
+ * several humans' predictions on one grid).  grids[h] points to a float32
+ * [n] array; out[i] = max_h grids[h][i] in FP64 of the FP32 values. */
+int orc_union_max(const float* const* grids, int n_humans, int64_t n, float* out) {
+  if (n_humans < 1 || n < 0) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    float m = grids[0][i];
+    for (int h = 1; h < n_humans; ++h)
+      if (grids[h][i] > m) m = grids[h][i];
+    out[i] = m;
+  }
+  return 0;
+}
