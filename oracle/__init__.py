@@ -82,22 +82,23 @@ def lib():
             L.orc_philox_bulk.restype = None
             L.orc_uniform24.argtypes = [u32]
             L.orc_uniform24.restype = d
-            L.orc_lattice_steps.argtypes = [i32, d, d, d, _i32p, _i32p]
+            L.orc_lattice_steps.argtypes = [i32, i32, _f64p, d, d, _i32p, _i32p]
             L.orc_lattice_steps.restype = i32
             L.orc_predict.argtypes = [
-                i32, d, d, i32, _f32p, i32, _f32p, d, d, d, i32, i32, d, d, _f64p,
+                i32, i32, _f64p, u32, d, i32, _f32p, i32, _f32p, d, d, d, i32, i32, d, d, _f64p,
                 i64, i32, u64, u32, u32, _nullable(_i64p), i64,
                 _nullable(_u32p), _nullable(_u32p), _nullable(_u8p), _nullable(_i32p),
                 _nullable(_i32p), i32]
             L.orc_predict.restype = i32
             L.orc_tie_check.argtypes = [
-                i32, d, d, i32, _f32p, i32, _f32p, d, d, d, d, d, _f64p,
+                i32, i32, _f64p, u32, d, i32, _f32p, i32, _f32p, d, d, d, d, d, _f64p,
                 i64, i32, u64, u32, u32, _nullable(_i64p), i64,
                 _i32p, _u8p, d, d, _i32p, _i32p, i32]
             L.orc_tie_check.restype = i32
-            L.orc_recover_controls.argtypes = [i32, _f32p, i32, _i32p, _nullable(_f64p)]
+            L.orc_recover_controls.argtypes = [i32, i32, _f64p, d, _f32p, i32, _i32p,
+                                               _nullable(_f64p)]
             L.orc_recover_controls.restype = i32
-            L.orc_belief_update.argtypes = [i32, d, d, i32, _f32p, i32, _f32p, _f32p, i32,
+            L.orc_belief_update.argtypes = [i32, i32, _f64p, d, i32, _f32p, i32, _f32p, _f32p, i32,
                                             _f64p, _nullable(_f64p), _nullable(_f64p), i32]
             L.orc_belief_update.restype = i32
             L.orc_loglik.argtypes = [i32, d, d, _f32p, _i32p, i32, i32, _f64p, i32, _f64p, i32,
@@ -106,7 +107,8 @@ def lib():
             L.orc_loglik_grad.argtypes = [i32, d, d, _f32p, _i32p, i32, i32, _f64p, i32, _f64p,
                                           i32, i32, _f64p, _f64p, _f64p]
             L.orc_loglik_grad.restype = i32
-            L.orc_simulate_tracks.argtypes = [i32, d, d, d, d, d, i32, i32, _f64p, _f32p, _f32p,
+            L.orc_simulate_tracks.argtypes = [i32, i32, _f64p, d, d, d, d, i32, i32, _f64p, _f32p,
+                                              _f32p,
                                               u64, u32, _nullable(_i64p), _nullable(_f32p)]
             L.orc_simulate_tracks.restype = i32
             L.orc_smooth.argtypes = [_u32p, i32, i32, i32, i64, d, i32, _nullable(_i64p), i64,
@@ -123,6 +125,12 @@ def default_threads() -> int:
         return max(1, len(os.sched_getaffinity(0)))
     except AttributeError:  # pragma: no cover
         return max(1, os.cpu_count() or 1)
+
+
+def _speeds(speed, speeds):
+    """Speeds of the control set (m/s) as FP64: `speeds` if given, else the one `speed`."""
+    v = [speed] if speeds is None else list(speeds)
+    return np.ascontiguousarray(v, np.float64)
 
 
 def _check(rc, what):
@@ -144,16 +152,18 @@ def uniform24(words: np.ndarray) -> np.ndarray:
     return ((w >> np.uint64(9)).astype(np.float64) * 2.0 + 1.0) * 2.0 ** -24
 
 
-def lattice_steps(K: int, speed: float, dt: float, cell: float):
-    Sx = np.empty(K, np.int32)
-    Sy = np.empty(K, np.int32)
-    _check(lib().orc_lattice_steps(K, speed, dt, cell, Sx, Sy), "lattice_steps")
+def lattice_steps(K: int, speed: float, dt: float, cell: float, speeds=None):
+    """Lattice steps of the U = S*K controls, u = s*K + k."""
+    v = _speeds(speed, speeds)
+    Sx = np.empty(K * v.size, np.int32)
+    Sy = np.empty(K * v.size, np.int32)
+    _check(lib().orc_lattice_steps(K, v.size, v, dt, cell, Sx, Sy), "lattice_steps")
     return Sx, Sy
 
 
 # ------------------------------------------------------------------ prediction
 def predict(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed=0, human=0, cycle=0,
-            idx=None, counts=True, trace=False, nthreads=None):
+            idx=None, counts=True, trace=False, nthreads=None, speeds=None, speed_mask=0):
     """Alg. 1 in FP64.  Returns dict with counts [H,ny,nx] uint32, offgrid [H],
     and with trace=True: trace_k [n,H] uint8, trace_pair [n] int32, trace_cell [n,H]."""
     x0, y0, cell, nx, ny = grid
@@ -169,7 +179,9 @@ def predict(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed=0, human=
     tk = np.zeros((n, H), np.uint8) if trace else None
     tp = np.zeros(n, np.int32) if trace else None
     tc = np.zeros((n, H), np.int32) if trace else None
-    rc = lib().orc_predict(K, speed, dt, B, beta, G, goals.reshape(-1), x0, y0, cell, nx, ny,
+    v = _speeds(speed, speeds)
+    rc = lib().orc_predict(K, v.size, v, speed_mask, dt, B, beta, G, goals.reshape(-1), x0, y0,
+                           cell, nx, ny,
                            float(z0[0]), float(z0[1]), belief, N, H, seed, human, cycle,
                            idx_arr, 0 if idx_arr is None else idx_arr.size,
                            None if cnt is None else cnt.reshape(-1), off,
@@ -181,7 +193,8 @@ def predict(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed=0, human=
 
 
 def tie_check(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed=0, human=0, cycle=0,
-              other_pair, other_k, window=1e-6, pair_window=0.0, idx=None, nthreads=None):
+              other_pair, other_k, window=1e-6, pair_window=0.0, idx=None, nthreads=None,
+              speeds=None, speed_mask=0):
     """Replay particles and classify another implementation's choices:
     status 0 identical, 1 first difference at a heading-CDF tie within `window`
     (or a pair-CDF tie within `pair_window`), 2 unexplained."""
@@ -193,7 +206,9 @@ def tie_check(*, K, speed, dt, beta, goals, grid, z0, belief, N, H, seed=0, huma
     n = N if idx_arr is None else idx_arr.size
     st = np.zeros(n, np.int32)
     first = np.zeros(n, np.int32)
-    rc = lib().orc_tie_check(K, speed, dt, beta.size, beta, goals.size // 2, goals, x0, y0, cell,
+    v = _speeds(speed, speeds)
+    rc = lib().orc_tie_check(K, v.size, v, speed_mask, dt, beta.size, beta, goals.size // 2,
+                             goals, x0, y0, cell,
                              float(z0[0]), float(z0[1]), belief, N, H, seed, human, cycle,
                              idx_arr, 0 if idx_arr is None else idx_arr.size,
                              np.ascontiguousarray(other_pair, np.int32),
@@ -210,12 +225,16 @@ def normalize(counts: np.ndarray, N: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- belief update
-def recover_controls(K: int, obs: np.ndarray):
+def recover_controls(K: int, obs: np.ndarray, speed: float = 1.0, dt: float = 1.0, speeds=None):
+    """Recovered controls u* = s*K + k* ([n_obs], -1 for a skipped step) and the
+    heading margin.  With one speed u* = k* whatever speed and dt are."""
     obs = np.ascontiguousarray(obs, np.float32).reshape(-1, 2)
     n = obs.shape[0] - 1
     ks = np.empty(max(n, 0), np.int32)
     margin = np.empty(max(n, 0), np.float64)
-    _check(lib().orc_recover_controls(K, obs.reshape(-1), n, ks, margin), "recover_controls")
+    v = _speeds(speed, speeds)
+    _check(lib().orc_recover_controls(K, v.size, v, dt, obs.reshape(-1), n, ks, margin),
+           "recover_controls")
     return ks, margin
 
 
@@ -224,7 +243,8 @@ def uniform_log_belief(G: int, B: int) -> np.ndarray:
     return np.full((G, B), -np.log(G * B), np.float64)
 
 
-def belief_update(*, K, speed, dt, beta, goals, obs, log_belief=None, sequential=False):
+def belief_update(*, K, speed, dt, beta, goals, obs, log_belief=None, sequential=False,
+                  speeds=None):
     """Returns (log_belief [G,B], belief [G,B], ell [n_obs,G,B])."""
     beta = np.ascontiguousarray(beta, np.float32)
     goals = np.ascontiguousarray(goals, np.float32).reshape(-1, 2)
@@ -235,7 +255,8 @@ def belief_update(*, K, speed, dt, beta, goals, obs, log_belief=None, sequential
     b = np.empty((G, B), np.float64)
     n = obs.shape[0] - 1
     ell = np.empty((max(n, 0), G, B), np.float64)
-    rc = lib().orc_belief_update(K, speed, dt, B, beta, G, goals.reshape(-1), obs.reshape(-1), n,
+    v = _speeds(speed, speeds)
+    rc = lib().orc_belief_update(K, v.size, v, dt, B, beta, G, goals.reshape(-1), obs.reshape(-1), n,
                                  lb.reshape(-1), b.reshape(-1), ell.reshape(-1), int(sequential))
     _check(rc, "belief_update")
     return lb, b, ell
@@ -277,7 +298,7 @@ def loglik_grad(*, K, speed, dt, tracks, lengths, goals, log_beta, dLL, per_trac
 
 
 # ----------------------------------------------------------------- synthetic humans
-def simulate_tracks(*, K, speed, dt, frame, start, beta, goal, T, seed=0, stream=0):
+def simulate_tracks(*, K, speed, dt, frame, start, beta, goal, T, seed=0, stream=0, speeds=None):
     """Returns (lattice [n,T+1,2] int64, positions [n,T+1,2] float32).
     frame = (x0, y0, cell) fixes the lattice."""
     x0, y0, cell = frame
@@ -287,7 +308,8 @@ def simulate_tracks(*, K, speed, dt, frame, start, beta, goal, T, seed=0, stream
     goal = np.ascontiguousarray(goal, np.float32).reshape(n, 2)
     lat = np.empty((n, T + 1, 2), np.int64)
     pos = np.empty((n, T + 1, 2), np.float32)
-    rc = lib().orc_simulate_tracks(K, speed, dt, x0, y0, cell, n, T, start.reshape(-1), beta,
+    v = _speeds(speed, speeds)
+    rc = lib().orc_simulate_tracks(K, v.size, v, dt, x0, y0, cell, n, T, start.reshape(-1), beta,
                                    goal.reshape(-1), seed, stream, lat.reshape(-1),
                                    pos.reshape(-1))
     _check(rc, "simulate_tracks")

@@ -15,9 +15,12 @@
  *
  * Conventions (readings of the paper that it leaves open; each one is listed
  * in the design notes):
- *   - headings theta_k = 2*pi*k/K counter-clockwise from +x, fixed speed v;
- *     one prediction step moves by v*dt*(cos theta_k, sin theta_k)
- *     (discretised 2-D kinematic model, Sec. III-A running example).
+ *   - headings theta_k = 2*pi*k/K counter-clockwise from +x; one prediction
+ *     step moves by v*dt*(cos theta_k, sin theta_k) (discretised 2-D
+ *     kinematic model, Sec. III-A running example).  The control set is
+ *     speeds {v_0..v_{S-1}} x headings, control u = s*K + k (S = 1: one fixed
+ *     speed).  A speed mask (bit s) removes the controls of the other speeds
+ *     from the prediction policy (Q = -inf, Sec. IV-B stationary humans).
  *   - Q(x,u;g) = -|x + v*dt*u - g|  (the running example's Q printed in the
  *     paper does not depend on the heading, so the next-state distance is used).
  *   - policy pi(k|x;beta,g) = exp(beta*Q_k) / sum_j exp(beta*Q_j)
@@ -108,48 +111,75 @@ static int64_t orc_cell_of(int64_t v) {
   return -((-v + 65535) / 65536);
 }
 
-int orc_lattice_steps(int K, double speed, double dt, double cell, int32_t* Sx, int32_t* Sy) {
-  if (K < 2 || K > ORC_MAXK || !(speed > 0) || !(dt > 0) || !(cell > 0)) return -1;
-  const double L = speed * dt;
+#define ORC_MAXS 8
+
+/* Control set: S speeds x K headings, u = s*K + k. */
+static int orc_check_controls(int K, int S, const double* speeds) {
+  if (K < 2 || S < 1 || S > ORC_MAXS || K * S > ORC_MAXK || !speeds) return -1;
+  for (int s = 0; s < S; ++s)
+    if (!(speeds[s] > 0)) return -1;
+  return 0;
+}
+
+int orc_lattice_steps(int K, int S, const double* speeds, double dt, double cell, int32_t* Sx,
+                      int32_t* Sy) {
+  if (orc_check_controls(K, S, speeds) || !(dt > 0) || !(cell > 0)) return -1;
   const double q = orc_pitch(cell);
-  for (int k = 0; k < K; ++k) {
-    const double th = 2.0 * ORC_PI * (double)k / (double)K;
-    Sx[k] = (int32_t)rint(L * cos(th) / q);
-    Sy[k] = (int32_t)rint(L * sin(th) / q);
+  for (int s = 0; s < S; ++s) {
+    const double L = speeds[s] * dt;
+    for (int k = 0; k < K; ++k) {
+      const double th = 2.0 * ORC_PI * (double)k / (double)K;
+      Sx[s * K + k] = (int32_t)rint(L * cos(th) / q);
+      Sy[s * K + k] = (int32_t)rint(L * sin(th) / q);
+    }
   }
   return 0;
 }
 
+/* allowed[u] = 1 for the controls whose speed bit is set in mask (mask 0: all). */
+static int orc_allowed(int K, int S, uint32_t mask, unsigned char* allowed) {
+  const uint32_t full = S >= 32 ? 0xFFFFFFFFu : ((1u << S) - 1u);
+  if (mask == 0) mask = full;
+  if ((mask & full) == 0) return -1;
+  for (int s = 0; s < S; ++s)
+    for (int k = 0; k < K; ++k) allowed[s * K + k] = (unsigned char)((mask >> s) & 1u);
+  return 0;
+}
+
 /* Continuous step vectors used by the belief update and the log-likelihood:
- * the FP32 roundings of v*dt*(cos theta_k, sin theta_k). */
-static void orc_cont_steps(int K, double speed, double dt, double* sx, double* sy) {
-  const double L = speed * dt;
-  for (int k = 0; k < K; ++k) {
-    const double th = 2.0 * ORC_PI * (double)k / (double)K;
-    sx[k] = (double)(float)(L * cos(th));
-    sy[k] = (double)(float)(L * sin(th));
+ * the FP32 roundings of v_s*dt*(cos theta_k, sin theta_k), u = s*K + k. */
+static void orc_cont_steps(int K, int S, const double* speeds, double dt, double* sx,
+                           double* sy) {
+  for (int s = 0; s < S; ++s) {
+    const double L = speeds[s] * dt;
+    for (int k = 0; k < K; ++k) {
+      const double th = 2.0 * ORC_PI * (double)k / (double)K;
+      sx[s * K + k] = (double)(float)(L * cos(th));
+      sy[s * K + k] = (double)(float)(L * sin(th));
+    }
   }
 }
 
 /* ------------------------------------------------------------------------ */
-/* Policy on the lattice: cumulative unnormalised weights C_k for a particle at
- * (X,Y), goal (GX,GY) and rationality beta.  d_k is the distance to the goal
- * after heading k; w_k = exp(-beta (d_k - min d)). */
-static void orc_lattice_cdf(int K, const int32_t* Sx, const int32_t* Sy, double q,
-                            int64_t X, int64_t Y, int64_t GX, int64_t GY, double beta,
-                            double* C) {
+/* Policy on the lattice: cumulative unnormalised weights C_u over the U
+ * controls for a particle at (X,Y), goal (GX,GY) and rationality beta.  d_u is
+ * the distance to the goal after control u; w_u = exp(-beta (d_u - min d))
+ * over the allowed controls, 0 for the others (allowed NULL: all). */
+static void orc_lattice_cdf(int U, const int32_t* Sx, const int32_t* Sy,
+                            const unsigned char* allowed, double q, int64_t X, int64_t Y,
+                            int64_t GX, int64_t GY, double beta, double* C) {
   double d[ORC_MAXK];
   double dmin = INFINITY;
-  for (int k = 0; k < K; ++k) {
-    const double ax = (double)(X + Sx[k] - GX) * q;
-    const double ay = (double)(Y + Sy[k] - GY) * q;
-    d[k] = hypot(ax, ay);
-    if (d[k] < dmin) dmin = d[k];
+  for (int u = 0; u < U; ++u) {
+    const double ax = (double)(X + Sx[u] - GX) * q;
+    const double ay = (double)(Y + Sy[u] - GY) * q;
+    d[u] = hypot(ax, ay);
+    if ((!allowed || allowed[u]) && d[u] < dmin) dmin = d[u];
   }
   double acc = 0.0;
-  for (int k = 0; k < K; ++k) {
-    acc += exp(-beta * (d[k] - dmin));
-    C[k] = acc;
+  for (int u = 0; u < U; ++u) {
+    if (!allowed || allowed[u]) acc += exp(-beta * (d[u] - dmin));
+    C[u] = acc;
   }
 }
 
@@ -184,12 +214,12 @@ static int orc_pick_pair(int J, const double* P, int last, double u) {
 /* Alg. 1 (hardware-accelerated human prediction) step by step, for particle
  * indices idx[0..n_idx) (or 0..N-1 when idx is NULL):
  *   draw (beta,g) once from the belief (bootstrapped belief, Sec. III-B);
- *   for t = 1..H: draw a heading from the Boltzmann policy at the particle's
- *   own state, move one step, emplace the new position on grid t.
+ *   for t = 1..H: draw a control u = s*K + k from the Boltzmann policy at the
+ *   particle's own state, move one step, emplace the new position on grid t.
  * counts [H][ny][nx] and offgrid [H] are accumulated (caller zeroes them).
- * trace_k [n][H] receives chosen headings, trace_pair [n] the pair index,
+ * trace_k [n][H] receives chosen controls u, trace_pair [n] the pair index,
  * trace_cell [n][H] the flattened cell (-1 when off the grid). */
-int orc_predict(int K, double speed, double dt,
+int orc_predict(int K, int S, const double* speeds, uint32_t speed_mask, double dt,
                 int B, const float* beta, int G, const float* goals,
                 double x0, double y0, double cell, int nx, int ny,
                 double zx, double zy, const double* belief,
@@ -198,9 +228,12 @@ int orc_predict(int K, double speed, double dt,
                 uint32_t* counts, uint32_t* offgrid,
                 uint8_t* trace_k, int32_t* trace_pair, int32_t* trace_cell,
                 int nthreads) {
-  if (K < 2 || K > ORC_MAXK || B < 1 || G < 1 || N < 1 || H < 1 || nx < 1 || ny < 1) return -1;
+  if (B < 1 || G < 1 || N < 1 || H < 1 || nx < 1 || ny < 1) return -1;
   int32_t Sx[ORC_MAXK], Sy[ORC_MAXK];
-  if (orc_lattice_steps(K, speed, dt, cell, Sx, Sy)) return -1;
+  unsigned char allowed[ORC_MAXK];
+  if (orc_lattice_steps(K, S, speeds, dt, cell, Sx, Sy)) return -1;
+  if (orc_allowed(K, S, speed_mask, allowed)) return -1;
+  const int U = K * S;
   const double q = orc_pitch(cell);
   const int J = G * B;
   double* P = (double*)malloc(sizeof(double) * J);
@@ -240,10 +273,10 @@ int orc_predict(int K, double speed, double dt,
       const double bt = (double)beta[b];
       int64_t X = X0, Y = Y0;
       for (int t = 1; t <= H; ++t) {
-        orc_lattice_cdf(K, Sx, Sy, q, X, Y, GX[g], GY[g], bt, C);
+        orc_lattice_cdf(U, Sx, Sy, allowed, q, X, Y, GX[g], GY[g], bt, C);
         const double u = orc_draw(seed, (uint32_t)i, (uint32_t)((t - 1) / 4), human, c3_head,
                                   (t - 1) % 4);
-        const int k = orc_pick(K, C, u);
+        const int k = orc_pick(U, C, u);
         X += Sx[k];
         Y += Sy[k];
         if (trace_k) trace_k[r * H + (t - 1)] = (uint8_t)k;
@@ -274,7 +307,7 @@ int orc_predict(int K, double speed, double dt,
  *   status 0 = identical, 1 = first difference explained by a CDF tie within
  *   `window` at that draw, 2 = unexplained difference;
  *   first[r] = first differing step (0 = pair draw, t>=1 = heading step, -1 none). */
-int orc_tie_check(int K, double speed, double dt,
+int orc_tie_check(int K, int S, const double* speeds, uint32_t speed_mask, double dt,
                   int B, const float* beta, int G, const float* goals,
                   double x0, double y0, double cell,
                   double zx, double zy, const double* belief,
@@ -283,7 +316,10 @@ int orc_tie_check(int K, double speed, double dt,
                   const int32_t* other_pair, const uint8_t* other_k, double window,
                   double pair_window, int32_t* status, int32_t* first, int nthreads) {
   int32_t Sx[ORC_MAXK], Sy[ORC_MAXK];
-  if (orc_lattice_steps(K, speed, dt, cell, Sx, Sy)) return -1;
+  unsigned char allowed[ORC_MAXK];
+  if (orc_lattice_steps(K, S, speeds, dt, cell, Sx, Sy)) return -1;
+  if (orc_allowed(K, S, speed_mask, allowed)) return -1;
+  const int U = K * S;
   const double q = orc_pitch(cell);
   const int J = G * B;
   double* P = (double*)malloc(sizeof(double) * J);
@@ -326,16 +362,16 @@ int orc_tie_check(int K, double speed, double dt,
     const double bt = (double)beta[b];
     int64_t X = X0, Y = Y0;
     for (int t = 1; t <= H; ++t) {
-      orc_lattice_cdf(K, Sx, Sy, q, X, Y, GX[g], GY[g], bt, C);
+      orc_lattice_cdf(U, Sx, Sy, allowed, q, X, Y, GX[g], GY[g], bt, C);
       const double u = orc_draw(seed, (uint32_t)i, (uint32_t)((t - 1) / 4), human,
                                 2u * cycle + 1u, (t - 1) % 4);
-      const int k = orc_pick(K, C, u);
+      const int k = orc_pick(U, C, u);
       const int ko = other_k[r * H + (t - 1)];
       if (ko != k) {
         first[r] = t;
         int ok = 0;
-        if (ko >= 0 && ko < K) {
-          const double tot = C[K - 1];
+        if (ko >= 0 && ko < U && allowed[ko]) {
+          const double tot = C[U - 1];
           if (ko > k) ok = (C[ko - 1] / tot - u) <= window;
           else ok = (u - C[ko] / tot) <= window;
         }
@@ -351,17 +387,21 @@ int orc_tie_check(int K, double speed, double dt,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Control recovery (flatness of the kinematic model: the heading follows from
- * two consecutive positions).  k* = argmax_k <dz, (cos,sin)theta_k>, lowest k
- * on ties; -1 when |dz| < 1e-9 m (no information, the step is skipped).
- * margin[t] (nullable) = best minus second-best dot product, for tie screening. */
-int orc_recover_controls(int K, const float* obs, int n_obs, int32_t* kstar, double* margin) {
-  if (K < 2 || K > ORC_MAXK || n_obs < 0) return -1;
+/* Control recovery (flatness of the kinematic model: the control follows from
+ * two consecutive positions): the control nearest to the displacement dz.
+ * Every speed shares the heading k* = argmax_k <dz, (cos,sin)theta_k> (lowest
+ * k on ties); the speed is the one whose step v_s dt is nearest to the
+ * projection p = <dz, (cos,sin)theta_k*> (lowest s on ties).  u* = s* K + k*;
+ * -1 when |dz| < 1e-9 m (no information, the step is skipped).
+ * margin[t] (nullable) = best minus second-best heading projection. */
+int orc_recover_controls(int K, int S, const double* speeds, double dt, const float* obs,
+                         int n_obs, int32_t* ustar, double* margin) {
+  if (orc_check_controls(K, S, speeds) || !(dt > 0) || n_obs < 0) return -1;
   for (int t = 0; t < n_obs; ++t) {
     const double dx = (double)obs[2 * (t + 1)] - (double)obs[2 * t];
     const double dy = (double)obs[2 * (t + 1) + 1] - (double)obs[2 * t + 1];
     if (hypot(dx, dy) < 1e-9) {
-      kstar[t] = -1;
+      ustar[t] = -1;
       if (margin) margin[t] = INFINITY;
       continue;
     }
@@ -373,13 +413,20 @@ int orc_recover_controls(int K, const float* obs, int n_obs, int32_t* kstar, dou
       if (v > bv) { second = bv; bv = v; best = k; }
       else if (v > second) second = v;
     }
-    kstar[t] = best;
+    int sb = 0;
+    double err = INFINITY;
+    for (int s = 0; s < S; ++s) {
+      const double e = fabs(speeds[s] * dt - bv);
+      if (e < err) { err = e; sb = s; }
+    }
+    ustar[t] = sb * K + best;
     if (margin) margin[t] = bv - second;
   }
   return 0;
 }
 
-/* log pi(k*|z;beta,g) for the continuous model (FP64, max-shifted log-sum-exp). */
+/* log pi(u*|z;beta,g) over the U controls of the continuous model (FP64,
+ * max-shifted log-sum-exp). */
 static double orc_log_policy(int K, const double* sx, const double* sy, double zx, double zy,
                              double gx, double gy, double beta, int kstar) {
   double d[ORC_MAXK];
@@ -400,15 +447,16 @@ static double orc_log_policy(int K, const double* sx, const double* sy, double z
  * `sequential` != 0 renormalises after every transition instead.
  * log_belief [G][B] in/out, belief [G][B] out (nullable), ell [n_obs][G][B]
  * per-transition log-likelihoods out (nullable). */
-int orc_belief_update(int K, double speed, double dt, int B, const float* beta,
+int orc_belief_update(int K, int S, const double* speeds, double dt, int B, const float* beta,
                       int G, const float* goals, const float* obs, int n_obs,
                       double* log_belief, double* belief, double* ell, int sequential) {
-  if (K < 2 || K > ORC_MAXK || B < 1 || G < 1 || n_obs < 0) return -1;
+  if (orc_check_controls(K, S, speeds) || !(dt > 0) || B < 1 || G < 1 || n_obs < 0) return -1;
   double sx[ORC_MAXK], sy[ORC_MAXK];
-  orc_cont_steps(K, speed, dt, sx, sy);
+  orc_cont_steps(K, S, speeds, dt, sx, sy);
+  const int U = K * S;
   int32_t* ks = (int32_t*)malloc(sizeof(int32_t) * (n_obs > 0 ? n_obs : 1));
   if (!ks) return -1;
-  orc_recover_controls(K, obs, n_obs, ks, NULL);
+  orc_recover_controls(K, S, speeds, dt, obs, n_obs, ks, NULL);
   const int J = G * B;
   double* acc = (double*)calloc((size_t)J, sizeof(double));
   for (int t = 0; t < n_obs; ++t) {
@@ -416,7 +464,7 @@ int orc_belief_update(int K, double speed, double dt, int B, const float* beta,
       for (int b = 0; b < B; ++b) {
         double l = 0.0;
         if (ks[t] >= 0)
-          l = orc_log_policy(K, sx, sy, (double)obs[2 * t], (double)obs[2 * t + 1],
+          l = orc_log_policy(U, sx, sy, (double)obs[2 * t], (double)obs[2 * t + 1],
                              (double)goals[2 * g], (double)goals[2 * g + 1], (double)beta[b],
                              ks[t]);
         if (ell) ell[((int64_t)t * G + g) * B + b] = l;
@@ -459,7 +507,7 @@ int orc_loglik(int K, double speed, double dt, const float* tracks, const int32_
                int per_track_beta, double* LL, int nthreads) {
   if (K < 2 || K > ORC_MAXK || N < 0 || Tmax < 0 || G < 1 || B < 1) return -1;
   double sx[ORC_MAXK], sy[ORC_MAXK];
-  orc_cont_steps(K, speed, dt, sx, sy);
+  orc_cont_steps(K, 1, &speed, dt, sx, sy);
   if (nthreads < 1) nthreads = 1;
   int err = 0;
 #pragma omp parallel for num_threads(nthreads) schedule(static)
@@ -468,7 +516,7 @@ int orc_loglik(int K, double speed, double dt, const float* tracks, const int32_
     const int len = lengths[n];
     if (len < 0 || len > Tmax) { err = 1; continue; }
     int32_t* ks = (int32_t*)malloc(sizeof(int32_t) * (len > 0 ? len : 1));
-    orc_recover_controls(K, z, len, ks, NULL);
+    orc_recover_controls(K, 1, &speed, dt, z, len, ks, NULL);
     for (int b = 0; b < B; ++b) {
       const double bt = exp(per_track_beta ? log_beta[(int64_t)n * B + b] : log_beta[b]);
       for (int g = 0; g < G; ++g) {
@@ -496,7 +544,7 @@ int orc_loglik_grad(int K, double speed, double dt, const float* tracks, const i
                     int per_track_beta, const double* dLL, double* dgoals, double* dlog_beta) {
   if (K < 2 || K > ORC_MAXK || N < 0 || Tmax < 0 || G < 1 || B < 1) return -1;
   double sx[ORC_MAXK], sy[ORC_MAXK];
-  orc_cont_steps(K, speed, dt, sx, sy);
+  orc_cont_steps(K, 1, &speed, dt, sx, sy);
   memset(dgoals, 0, sizeof(double) * 2 * G);
   memset(dlog_beta, 0, sizeof(double) * (per_track_beta ? (int64_t)N * B : B));
   double d[ORC_MAXK], yx[ORC_MAXK], yy[ORC_MAXK], p[ORC_MAXK];
@@ -505,7 +553,7 @@ int orc_loglik_grad(int K, double speed, double dt, const float* tracks, const i
     const int len = lengths[n];
     if (len < 0 || len > Tmax) return -1;
     int32_t* ks = (int32_t*)malloc(sizeof(int32_t) * (len > 0 ? len : 1));
-    orc_recover_controls(K, z, len, ks, NULL);
+    orc_recover_controls(K, 1, &speed, dt, z, len, ks, NULL);
     for (int t = 0; t < len; ++t) {
       if (ks[t] < 0) continue;
       const double zx = (double)z[2 * t], zy = (double)z[2 * t + 1];
@@ -549,12 +597,14 @@ int orc_loglik_grad(int K, double speed, double dt, const float* tracks, const i
 /* Synthetic humans: n tracks of T lattice steps, each driven by the same
  * Boltzmann policy with its own fixed (beta, goal).  Positions are reported on
  * the lattice (lat, [n][T+1][2]) and as FP32 metres (pos, origin + X*q). */
-int orc_simulate_tracks(int K, double speed, double dt, double x0, double y0, double cell,
-                        int n, int T, const double* start, const float* beta, const float* goal,
-                        uint64_t seed, uint32_t stream, int64_t* lat, float* pos) {
-  if (K < 2 || K > ORC_MAXK || n < 0 || T < 0) return -1;
+int orc_simulate_tracks(int K, int S, const double* speeds, double dt, double x0, double y0,
+                        double cell, int n, int T, const double* start, const float* beta,
+                        const float* goal, uint64_t seed, uint32_t stream, int64_t* lat,
+                        float* pos) {
+  if (n < 0 || T < 0) return -1;
   int32_t Sx[ORC_MAXK], Sy[ORC_MAXK];
-  if (orc_lattice_steps(K, speed, dt, cell, Sx, Sy)) return -1;
+  if (orc_lattice_steps(K, S, speeds, dt, cell, Sx, Sy)) return -1;
+  const int U = K * S;
   const double q = orc_pitch(cell);
   double C[ORC_MAXK];
   for (int r = 0; r < n; ++r) {
@@ -564,10 +614,10 @@ int orc_simulate_tracks(int K, double speed, double dt, double x0, double y0, do
     const int64_t GY = orc_to_lattice((double)goal[2 * r + 1], y0, cell);
     for (int t = 0; t <= T; ++t) {
       if (t > 0) {
-        orc_lattice_cdf(K, Sx, Sy, q, X, Y, GX, GY, (double)beta[r], C);
+        orc_lattice_cdf(U, Sx, Sy, NULL, q, X, Y, GX, GY, (double)beta[r], C);
         const double u = orc_draw(seed, (uint32_t)r, (uint32_t)((t - 1) / 4), stream,
                                   ORC_SIM_TAG, (t - 1) % 4);
-        const int k = orc_pick(K, C, u);
+        const int k = orc_pick(U, C, u);
         X += Sx[k];
         Y += Sy[k];
       }
