@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define CAP_ABI_VERSION 1
+#define CAP_ABI_VERSION 2
 #define CAP_MAX_K 32   /* headings per model                       */
 #define CAP_MAX_B 16   /* rationality values per model             */
 #define CAP_MAX_G 64   /* goals per model                          */
@@ -131,6 +131,32 @@ cap_status cap_predict_occupancy(const cap_model* model, const cap_grid* grid,
 cap_status cap_normalize(const uint32_t* counts_dev, int64_t n_cells, int32_t N,
                          float* probs_dev, void* stream);
 
+/* Gaussian-smoothed occupancy probabilities: the Gaussian convolution of the
+ * particle batch before emplacement (Sec. III-B), taken as the convolution of
+ * each step's point histogram with the discrete kernel w(dx) w(dy),
+ *   w(d) = exp(-d^2 / (2 sigma^2)) / sum_{|e| <= radius} exp(-e^2 / (2 sigma^2)),
+ * over the square window |dx|, |dy| <= radius (cells), counts outside the grid
+ * being zero, divided by N:
+ *   probs[t][y][x] = sum_{dx,dy} w(dx) w(dy) counts[t][y-dy][x-dx] / N.
+ *   counts_dev [H][ny][nx] uint32 (device), probs_dev [H][ny][nx] FP32
+ *   (device, must not alias counts); radius in [0, 16] (0 gives count / N);
+ *   sigma > 0 in cells when radius > 0.  FP32 arithmetic: relative error at
+ *   most (4 radius + 6) 2^-24 per output.  Asynchronous on `stream`.
+ * Errors: CAP_E_INVALID for a bad size, radius, sigma or pointer. */
+cap_status cap_smooth_occupancy(const uint32_t* counts_dev, int32_t H, int32_t ny, int32_t nx,
+                                int32_t N, double sigma, int32_t radius, float* probs_dev,
+                                void* stream);
+
+/* Union of several humans' predictions on one grid by the point-wise maximum
+ * (Sec. IV-B): out[i] = max_h grids[h][i], i < n_cells.
+ *   grids: HOST array of n_humans (1..CAP_MAX_SLOTS) DEVICE pointers, each to
+ *   at least n_cells FP32 probabilities (no NaN) laid out alike, e.g. [H][ny][nx]
+ *   of humans sharing one grid frame; out_dev [n_cells] FP32 (device), may
+ *   alias grids[0].  The pointer array is read before the call returns.
+ * Errors: CAP_E_INVALID for a bad count or a NULL pointer. */
+cap_status cap_union_max(const float* const* grids, int32_t n_humans, int64_t n_cells,
+                         float* out_dev, void* stream);
+
 /* Raw Philox4x32-10 blocks of the library's generator, for counters
  * (c0 + i, c1, c2, c3), i < n, key (seed lo, seed hi): out_dev [n][4] uint32.
  * Exposed so that the random-number contract above can be checked directly. */
@@ -208,6 +234,8 @@ typedef struct cap_plan_config {
   int32_t particles_per_thread; /* 0 = default; else 1, 2 or 4                  */
   int32_t lds_bytes;            /* 0 = default; LDS histogram window per block  */
   int32_t grid_blocks;          /* 0 = default; persistent blocks per launch    */
+  int32_t max_smooth_radius;    /* 0 = no smoothing stage; 1..16 = largest radius a
+                                   slot may ask for (sizes the stage's LDS tile) */
 } cap_plan_config;
 
 #define CAP_MAX_SLOTS 256
@@ -227,6 +255,10 @@ typedef struct cap_slot_desc {
   double* log_belief_dev;       /* [G][B] FP64 belief state, caller-owned, in/out */
   double* belief_dev;           /* [ring][G][B] FP64 posterior out (read by the rollout) */
   int32_t reset_belief;         /* 1: write the uniform prior before the first update */
+  int32_t smooth_radius;        /* 0: probs = count / N; 1..max_smooth_radius: probs
+                                   are the Gaussian-smoothed occupancy of
+                                   cap_smooth_occupancy (requires probs_dev)       */
+  double smooth_sigma;          /* kernel width in cells, > 0 when smooth_radius > 0 */
 } cap_slot_desc;
 
 cap_status cap_plan_create(const cap_plan_config* cfg, cap_plan** out);
@@ -241,7 +273,9 @@ cap_status cap_plan_clear_slot(cap_plan* plan, int32_t slot);
 cap_status cap_plan_stage_obs(cap_plan* plan, int32_t slot, const float* xy, int32_t n_new);
 /* Run one cycle on `stream`: copy the compact descriptors (with staged
  * observations) to ring entry cycle % ring and launch the captured graphs:
- * belief update -> grid clear -> persistent batched rollout -> normalisation.
+ * belief update -> grid clear -> persistent batched rollout -> normalisation
+ * (-> Gaussian smoothing of the slots that ask for it, when the plan was
+ * created with max_smooth_radius > 0).
  * Every active slot is predicted from its newest observed position.  The
  * staging area is reusable when this returns.  cycle < 2^31 - 1. */
 cap_status cap_plan_run(cap_plan* plan, uint64_t seed, uint32_t cycle, void* stream);

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcapred.so")
-SOURCES = ["abi.hip", "belief.hip", "predict.hip", "loglik.hip", "plan.hip", "probe.hip"]
+SOURCES = ["abi.hip", "belief.hip", "predict.hip", "loglik.hip", "plan.hip", "probe.hip",
+           "smooth.hip"]
 ARCH = "gfx950"
 
 

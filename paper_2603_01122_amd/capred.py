@@ -51,7 +51,8 @@ class cap_plan_config(C.Structure):
     _fields_ = [("n_slots", C.c_int32), ("K", C.c_int32), ("speed", C.c_double),
                 ("dt", C.c_double), ("max_obs", C.c_int32), ("ring", C.c_int32),
                 ("block_threads", C.c_int32), ("particles_per_thread", C.c_int32),
-                ("lds_bytes", C.c_int32), ("grid_blocks", C.c_int32)]
+                ("lds_bytes", C.c_int32), ("grid_blocks", C.c_int32),
+                ("max_smooth_radius", C.c_int32)]
 
 
 class cap_slot_desc(C.Structure):
@@ -61,7 +62,8 @@ class cap_slot_desc(C.Structure):
                 ("last_xy", C.c_float * 2), ("counts_dev", C.c_void_p),
                 ("offgrid_dev", C.c_void_p), ("probs_dev", C.c_void_p),
                 ("log_belief_dev", C.c_void_p), ("belief_dev", C.c_void_p),
-                ("reset_belief", C.c_int32)]
+                ("reset_belief", C.c_int32), ("smooth_radius", C.c_int32),
+                ("smooth_sigma", C.c_double)]
 
 
 _vp, _i32, _u32, _u64, _i64, _d, _sz = (C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64,
@@ -83,6 +85,8 @@ _sig("cap_belief_reset", _i32, _i32, _i32, _vp, _vp)
 _sig("cap_predict_occupancy", _i32, C.POINTER(cap_model), C.POINTER(cap_grid),
      C.POINTER(C.c_double), _vp, _i32, _i32, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp)
 _sig("cap_normalize", _i32, _vp, _i64, _i32, _vp, _vp)
+_sig("cap_smooth_occupancy", _i32, _vp, _i32, _i32, _i32, _i32, C.c_double, _i32, _vp, _vp)
+_sig("cap_union_max", _i32, C.POINTER(_vp), _i32, _i64, _vp, _vp)
 _sig("cap_simulate_tracks", _i32, _i32, _d, _d, _d, _d, _d, _i32, _i32, _vp, _vp, _vp, _u64, _u32,
      _vp, _vp, _vp)
 _sig("cap_loglik", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp)
@@ -94,7 +98,8 @@ _sig("cap_probe", _i32, _i32, _i64, _i32, _vp, _vp)
 _sig("cap_copy", _i32, _vp, _vp, _sz, _vp)
 EXPORTED = ["cap_probe", "cap_copy", "cap_philox_blocks", "cap_abi_version", "cap_last_error", "cap_device_cu_count", "cap_belief_update",
             "cap_belief_reset", "cap_predict_occupancy", "cap_normalize", "cap_simulate_tracks",
-            "cap_loglik", "cap_loglik_backward", "cap_loglik_backward_workspace"]
+            "cap_loglik", "cap_loglik_backward", "cap_loglik_backward_workspace",
+            "cap_smooth_occupancy", "cap_union_max"]
 if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_create", _i32, C.POINTER(cap_plan_config), C.POINTER(_vp))
     _sig("cap_plan_destroy", None, _vp)
@@ -240,6 +245,36 @@ def normalize(counts: torch.Tensor, N: int, probs: Optional[torch.Tensor] = None
     return probs
 
 
+def smooth_occupancy(counts: torch.Tensor, N: int, sigma: float = 1.0, radius: int = 3,
+                     probs: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Gaussian-smoothed probabilities of a [H, ny, nx] count stack (FP32)."""
+    if counts.dim() != 3:
+        raise ValueError("counts must be [H, ny, nx]")
+    H, ny, nx = counts.shape
+    if probs is None:
+        probs = torch.empty(counts.shape, dtype=torch.float32, device=counts.device)
+    _check(_lib.cap_smooth_occupancy(_ptr(counts, torch.int32, "counts"), H, ny, nx, N,
+                                     float(sigma), int(radius),
+                                     _ptr(probs, torch.float32, "probs", tuple(counts.shape)),
+                                     _stream(stream)), "cap_smooth_occupancy")
+    return probs
+
+
+def union_max(grids: Sequence[torch.Tensor], out: Optional[torch.Tensor] = None,
+              stream=None) -> torch.Tensor:
+    """Point-wise maximum over equally shaped FP32 grids on one device."""
+    if not grids:
+        raise ValueError("at least one grid is needed")
+    shape = tuple(grids[0].shape)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=grids[0].device)
+    ptrs = (_vp * len(grids))(*[_ptr(g, torch.float32, "grid", shape) for g in grids])
+    _check(_lib.cap_union_max(ptrs, len(grids), grids[0].numel(),
+                              _ptr(out, torch.float32, "out", shape), _stream(stream)),
+           "cap_union_max")
+    return out
+
+
 def philox_blocks(n: int, c0: int, c1: int, c2: int, c3: int, seed: int, device="cuda",
                   stream=None) -> torch.Tensor:
     """Raw Philox4x32-10 blocks for counters (c0+i, c1, c2, c3): int32 view [n, 4]."""
@@ -367,9 +402,9 @@ class Plan:
 
     def __init__(self, K: int, speed: float, dt: float, n_slots: int, max_obs: int = 1,
                  ring: int = 2, block_threads: int = 0, particles_per_thread: int = 0,
-                 lds_bytes: int = 0, grid_blocks: int = 0):
+                 lds_bytes: int = 0, grid_blocks: int = 0, max_smooth_radius: int = 0):
         cfg = cap_plan_config(n_slots, K, speed, dt, max_obs, ring, block_threads,
-                              particles_per_thread, lds_bytes, grid_blocks)
+                              particles_per_thread, lds_bytes, grid_blocks, max_smooth_radius)
         h = C.c_void_p()
         _check(_lib.cap_plan_create(C.byref(cfg), C.byref(h)), "cap_plan_create")
         self._h = h
@@ -394,7 +429,9 @@ class Plan:
         return {f: getattr(c, f) for f, _ in cap_plan_config._fields_}
 
     def admit(self, slot: int, human_id: int, model: Model, grid, N: int, H: int,
-              last_xy, buffers: SlotBuffers, reset_belief: bool = True):
+              last_xy, buffers: SlotBuffers, reset_belief: bool = True,
+              smooth: Optional[Tuple[float, int]] = None):
+        """smooth = (sigma, radius) in cells asks for Gaussian-smoothed probabilities."""
         if model.K != self.K:
             raise ValueError("model K differs from the plan's")
         desc = cap_slot_desc()
@@ -413,6 +450,8 @@ class Plan:
         desc.belief_dev = _ptr(buffers.belief, torch.float64, "belief",
                                (self.ring, model.G, model.B))
         desc.reset_belief = 1 if reset_belief else 0
+        if smooth is not None:
+            desc.smooth_sigma, desc.smooth_radius = float(smooth[0]), int(smooth[1])
         _check(_lib.cap_plan_set_slot(self._h, slot, C.byref(desc)), "cap_plan_set_slot")
         self.buffers[slot] = buffers
 

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "belief.hpp"
+#include "smooth.hpp"
 
 namespace capred {
 
@@ -32,6 +33,8 @@ struct SlotDev {
   int32_t n_obs;           // new transitions this cycle
   int32_t reset;           // write the uniform prior before updating
   float obs[(kMaxObs + 1) * 2];
+  int32_t smooth_r;        // 0: probs = count / N; > 0: Gaussian-smoothed probs
+  SmoothWeights smooth_w;  // normalised 1-D kernel, smooth_w.w[d + smooth_r]
 };
 
 struct CycleHeader {
@@ -39,6 +42,7 @@ struct CycleHeader {
   int32_t n_active, n_tiles, per_tile;
   int32_t tile_begin[CAP_MAX_SLOTS + 1];
   int32_t chunk_begin[CAP_MAX_SLOTS + 1];  // prefix of grid chunks (kChunk cells)
+  int32_t smooth_begin[CAP_MAX_SLOTS + 1]; // prefix of smoothing tiles
 };
 
 __device__ __forceinline__ const SlotDev* slots_of(const uint8_t* base) {
@@ -114,7 +118,7 @@ __global__ void __launch_bounds__(256)
   for (int c = c0 + (int)blockIdx.x; c < c1; c += (int)gridDim.x) {
     const int s = __builtin_amdgcn_readfirstlane(slot_of_chunk(H, c));
     float* p = sl[s].probs;
-    if (!p) continue;
+    if (!p || sl[s].smooth_r > 0) continue;
     const uint32_t* q = sl[s].rd.counts;
     const float N = (float)sl[s].rd.N;
     const int64_t n = sl[s].n_cells;
@@ -140,6 +144,41 @@ __global__ void __launch_bounds__(256)
     } else {
       for (int64_t v = off + threadIdx.x; v < end; v += blockDim.x) p[v] = (float)q[v] / N;
     }
+  }
+}
+
+// Smoothing tiles (step, band of kBandRows rows, 256 columns) of every slot
+// that asks for Gaussian-smoothed probabilities, as one index space
+// (smooth_begin prefix) walked by a persistent grid.
+__global__ void __launch_bounds__(kSmoothThreads)
+    plan_smooth_kernel(const uint8_t* __restrict__ base, int only) {
+  extern __shared__ float tile[];
+  const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
+  const SlotDev* sl = slots_of(base);
+  const int na = H->n_active;
+  const int b0 = only >= 0 ? (only < na ? H->smooth_begin[only] : 0) : 0;
+  const int b1 = only >= 0 ? (only < na ? H->smooth_begin[only + 1] : 0) : H->smooth_begin[na];
+  for (int b = b0 + (int)blockIdx.x; b < b1; b += (int)gridDim.x) {
+    int lo = 0, hi = na;  // largest s with smooth_begin[s] <= b
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (H->smooth_begin[mid] <= b) lo = mid;
+      else hi = mid;
+    }
+    const int s = __builtin_amdgcn_readfirstlane(lo);
+    const SlotDev& sd = sl[s];
+    const int nx = sd.rd.nx, ny = sd.rd.ny;
+    const int tx = (nx + kSmoothThreads - 1) / kSmoothThreads;
+    const int ty = (ny + kBandRows - 1) / kBandRows;
+    const int local = b - H->smooth_begin[s];
+    const int t = local / (tx * ty);
+    const int rem = local - t * tx * ty;
+    const int by = rem / tx, bx = rem - by * tx;
+    const size_t plane = (size_t)ny * nx;
+    smooth_block(sd.rd.counts + (size_t)t * plane, sd.probs + (size_t)t * plane, ny, nx,
+                 sd.smooth_r, (float)sd.rd.N, sd.smooth_w.w, by * kBandRows,
+                 bx * kSmoothThreads, tile);
+    __syncthreads();  // the next tile rewrites `tile`
   }
 }
 
@@ -239,6 +278,7 @@ struct cap_plan {
   size_t entry_bytes = 0;
   int cap_words = 0;            // LDS window words per buffer
   int grid_blocks = 0;
+  int smooth_blocks = 0;        // persistent blocks of the smoothing stage (0: no stage)
   int per_tile = 0;
   const void* rollout_fn[2] = {nullptr, nullptr};      // [shift variant]
   const void* rollout_one_fn[2] = {nullptr, nullptr};
@@ -314,6 +354,10 @@ static cap_status record_graphs(cap_plan* p, Entry& e) {
     cap_status st = launch_rollout(p, e, v, s);
     hipLaunchKernelGGL(plan_normalize_kernel, dim3(4096), dim3(256), 0, s, (const uint8_t*)e.dev,
                        minus1);
+    if (p->smooth_blocks > 0)
+      hipLaunchKernelGGL(plan_smooth_kernel, dim3(p->smooth_blocks), dim3(kSmoothThreads),
+                         smooth_lds_bytes(p->cfg.max_smooth_radius), s, (const uint8_t*)e.dev,
+                         minus1);
     hipError_t err = hipStreamEndCapture(s, &g);
     if (st != CAP_OK) return st;
     if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
@@ -348,7 +392,7 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
   H->seed_hi = (uint32_t)(seed >> 32);
   H->cycle = cycle;
   H->per_tile = p->per_tile;
-  int n = 0, tiles = 0, chunks = 0, variant = 0;
+  int n = 0, tiles = 0, chunks = 0, sblocks = 0, variant = 0;
   int64_t parts = 0, steps = 0;
   for (auto& hs : p->slots) {
     if (!hs.active) continue;
@@ -379,14 +423,19 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
     sd.rd.Y0 = (int32_t)lattice_coord((double)hs.last[1], hs.grid.y0, hs.grid.cell);
     H->tile_begin[n] = tiles;
     H->chunk_begin[n] = chunks;
+    H->smooth_begin[n] = sblocks;
     tiles += (int)((sd.rd.N + p->per_tile - 1) / p->per_tile);
     chunks += (int)((hs.n_cells + kChunk - 1) / kChunk);
+    if (sd.smooth_r > 0 && sd.probs)
+      sblocks += sd.rd.H * ((sd.rd.ny + kBandRows - 1) / kBandRows) *
+                 ((sd.rd.nx + kSmoothThreads - 1) / kSmoothThreads);
     parts += sd.rd.N;
     steps += (int64_t)sd.rd.N * sd.rd.H;
     ++n;
   }
   H->tile_begin[n] = tiles;
   H->chunk_begin[n] = chunks;
+  H->smooth_begin[n] = sblocks;
   H->n_active = n;
   p->last_variant = variant;
   H->n_tiles = tiles;
@@ -439,6 +488,8 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
   if (cfg.lds_bytes == 0) cfg.lds_bytes = 40 * 1024;
   if (cfg.lds_bytes < 2048 || cfg.lds_bytes > 144 * 1024)
     return fail(CAP_E_INVALID, "lds_bytes must be in [2 KiB, 144 KiB]");
+  if (cfg.max_smooth_radius < 0 || cfg.max_smooth_radius > kMaxSmoothRadius)
+    return fail(CAP_E_INVALID, "max_smooth_radius must be in [0, 16]");
   cap_plan* p = new cap_plan();
   p->cfg = cfg;
   p->slots.resize(cfg.n_slots);
@@ -468,6 +519,20 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
   if (cfg.grid_blocks == 0) cfg.grid_blocks = std::max(1, cus) * per_cu;
   p->cfg.grid_blocks = cfg.grid_blocks;
   p->grid_blocks = cfg.grid_blocks;
+  if (cfg.max_smooth_radius > 0) {
+    const size_t sl = smooth_lds_bytes(cfg.max_smooth_radius);
+    (void)hipFuncSetAttribute((const void*)plan_smooth_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sl);
+    int pc = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, (const void*)plan_smooth_kernel,
+                                                     kSmoothThreads, sl);
+    if (e != hipSuccess || pc < 1) {
+      destroy_plan(p);
+      return e != hipSuccess ? hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor")
+                             : fail(CAP_E_INVALID, "smoothing tile does not fit a CU");
+    }
+    p->smooth_blocks = std::max(1, cus) * pc;
+  }
   p->entry_bytes = header_bytes(cfg.n_slots);
   hipError_t he;
 #define CAP_TRY(call)                       \
@@ -520,6 +585,11 @@ extern "C" cap_status cap_plan_set_slot(cap_plan* p, int32_t slot, const cap_slo
   if ((st = check_grid(&d->grid)) != CAP_OK) return st;
   if (!d->counts_dev || !d->log_belief_dev || !d->belief_dev)
     return fail(CAP_E_INVALID, "counts, log_belief and belief buffers are required");
+  if ((st = check_smoothing(d->smooth_sigma, d->smooth_radius, p->cfg.max_smooth_radius)) !=
+      CAP_OK)
+    return st;
+  if (d->smooth_radius > 0 && !d->probs_dev)
+    return fail(CAP_E_INVALID, "smoothing needs probs_dev");
   HostSlot ns;
   std::memset(&ns.tmpl, 0, sizeof(SlotDev));
   st = make_rollout_desc(m.K, m.speed, m.dt, m.B, m.beta, m.G, m.goals, d->grid, d->N, d->H,
@@ -534,6 +604,8 @@ extern "C" cap_status cap_plan_set_slot(cap_plan* p, int32_t slot, const cap_slo
   ns.tmpl.rd.human = d->human_id;
   ns.tmpl.bm = make_belief_model(m.K, m.speed, m.dt, m.B, m.beta, m.G, m.goals);
   ns.tmpl.log_belief = d->log_belief_dev;
+  ns.tmpl.smooth_r = d->smooth_radius;
+  smooth_weights(d->smooth_sigma, d->smooth_radius, &ns.tmpl.smooth_w);
   ns.counts = d->counts_dev;
   ns.offgrid = d->offgrid_dev;
   ns.probs = d->probs_dev;
@@ -629,9 +701,14 @@ extern "C" cap_status cap_plan_run_plain(cap_plan* p, uint64_t seed, uint32_t cy
     void* args[] = {(void*)&base, (void*)&si, (void*)&p->cap_words};
     CAP_HIP(hipLaunchKernel(p->rollout_one_fn[sl[i].rd.shift ? 1 : 0], dim3(tiles), dim3(p->cfg.block_threads), args,
                             window_lds_bytes(p->cap_words, p->per_tile), s));
-    if (sl[i].probs) {
+    if (sl[i].probs && sl[i].smooth_r == 0) {
       const unsigned nb = (unsigned)std::min<size_t>((n + kChunk - 1) / kChunk, 4096);
       hipLaunchKernelGGL(plan_normalize_kernel, dim3(nb), dim3(256), 0, s, base, i);
+    }
+    if (sl[i].probs && sl[i].smooth_r > 0) {
+      const int nb = std::min(H->smooth_begin[i + 1] - H->smooth_begin[i], 4096);
+      hipLaunchKernelGGL(plan_smooth_kernel, dim3(nb), dim3(kSmoothThreads),
+                         smooth_lds_bytes(sl[i].smooth_r), s, base, i);
     }
   }
   if (H->n_active == 0) CAP_HIP(hipEventRecord(p->ev_update, s));

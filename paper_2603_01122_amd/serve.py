@@ -23,7 +23,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import time
-from typing import Dict, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -40,6 +40,7 @@ class HumanRequest:
     H: int
     last_xy: Sequence[float]
     log_belief: Optional[np.ndarray] = None   # carried state; None = uniform prior
+    smooth: Optional[Tuple[float, int]] = None  # (sigma, radius) cells: smoothed probabilities
 
 
 @dataclasses.dataclass
@@ -60,9 +61,10 @@ class Server:
     def __init__(self, K: int, speed: float, dt: float, n_slots: int, max_H: int, max_nx: int,
                  max_ny: int, max_G: int, max_B: int, ring: int = 2, n_streams: int = 2,
                  particle_budget: Optional[int] = None, seed: int = 0, probs: bool = True,
-                 tuning: Optional[dict] = None, device="cuda"):
+                 tuning: Optional[dict] = None, max_smooth_radius: int = 0, device="cuda"):
         tuning = tuning or {}
-        self.plan = capred.Plan(K, speed, dt, n_slots, max_obs=1, ring=ring, **tuning)
+        self.plan = capred.Plan(K, speed, dt, n_slots, max_obs=1, ring=ring,
+                                max_smooth_radius=max_smooth_radius, **tuning)
         self.K, self.ring, self.seed = K, ring, seed
         self.max = (max_H, max_nx, max_ny, max_G, max_B)
         cells = max_H * max_nx * max_ny
@@ -123,7 +125,7 @@ class Server:
                 if r.log_belief is not None:
                     buf.log_belief.copy_(torch.as_tensor(r.log_belief, dtype=torch.float64))
                 self.plan.admit(s, r.hid, r.model, r.grid, r.N, r.H, r.last_xy, buf,
-                                reset_belief=r.log_belief is None)
+                                reset_belief=r.log_belief is None, smooth=r.smooth)
                 self.slot_of[r.hid] = s
                 self.req[r.hid] = r
                 self.in_use += r.N

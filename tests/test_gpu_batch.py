@@ -52,18 +52,19 @@ def small_scene(n=6, N_div=16, H=30):
     return hs
 
 
-def make_server(cap, humans, ring=2, n_streams=2, slots=None, **tuning):
+def make_server(cap, humans, ring=2, n_streams=2, slots=None, max_smooth_radius=0, **tuning):
     from paper_2603_01122_amd.serve import Server
     h0 = humans[0]
     return Server(h0.K, h0.speed, h0.dt, slots or len(humans), max(h.H for h in humans),
                   max(h.grid[3] for h in humans), max(h.grid[4] for h in humans),
                   max(h.G for h in humans), max(h.B for h in humans), ring=ring,
-                  n_streams=n_streams, tuning=tuning or None)
+                  n_streams=n_streams, tuning=tuning or None,
+                  max_smooth_radius=max_smooth_radius)
 
 
-def request(cap, h, last):
+def request(cap, h, last, smooth=None):
     from paper_2603_01122_amd.serve import HumanRequest
-    return HumanRequest(h.hid, cap.model_of(h), h.grid, h.N, h.H, last)
+    return HumanRequest(h.hid, cap.model_of(h), h.grid, h.N, h.H, last, smooth=smooth)
 
 
 def snapshot(srv, hid, c):
@@ -218,6 +219,56 @@ def test_two_streams_overlap_equals_one(orc, cap):
                 assert np.array_equal(u, v)
     one.close()
     two.close()
+
+
+def test_batched_smoothing(orc, cap):
+    """Slots asking for Gaussian-smoothed probabilities (the smoothing stage in
+    the cycle's graph) get exactly cap_smooth_occupancy of their counts, in the
+    batched and in the per-human launch; the others keep count / N; the
+    smoothed grids agree with the oracle's direct sum within (4r + 6) 2^-24."""
+    humans = small_scene(n=5, N_div=8, H=20)
+    tr = tracks_for(orc, humans, 4)
+    sm = {humans[0].hid: (1.0, 3), humans[2].hid: (2.0, 6), humans[3].hid: (0.8, 1)}
+    note("batched smoothing, 5 humans (3 smoothed), 3 cycles")
+    A = make_server(cap, humans, max_smooth_radius=6)
+    Bp = make_server(cap, humans, max_smooth_radius=6)
+    for h in humans:
+        A.submit(request(cap, h, tr[h.hid][0], smooth=sm.get(h.hid)))
+        Bp.submit(request(cap, h, tr[h.hid][0], smooth=sm.get(h.hid)))
+    for c in range(3):
+        obs = {h.hid: tr[h.hid][c + 1] for h in humans}
+        A.step(obs)
+        Bp.step(obs, plain=True)
+        A.drain()
+        Bp.drain()
+        for h in humans:
+            a = snapshot(A, h.hid, c)
+            b = snapshot(Bp, h.hid, c)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (c, h.hid)
+            counts = torch.tensor(a[0], device="cuda")
+            if h.hid in sm:
+                sigma, r = sm[h.hid]
+                ref = cap.smooth_occupancy(counts, h.N, sigma, r)
+                torch.cuda.synchronize()
+                assert np.array_equal(ref.cpu().numpy(), a[1])
+                if c == 2:
+                    o = orc.smooth(a[0].view(np.uint32), h.N, sigma, r)
+                    assert np.all(np.abs(a[1] - o) <= (4 * r + 6) * 2.0 ** -24 * o)
+            else:
+                assert np.array_equal(cap.normalize(counts, h.N).cpu().numpy(), a[1])
+    A.close()
+    Bp.close()
+    p = cap.Plan(16, 1.2, 0.02, 1, max_obs=1, max_smooth_radius=2)
+    h = humans[0]
+    buf = cap.SlotBuffers.allocate(cap.model_of(h), h.grid, 5, 2)
+    with pytest.raises(cap.CapError):
+        p.admit(0, 1, cap.model_of(h), h.grid, 100, 5, h.start, buf, smooth=(1.0, 3))
+    with pytest.raises(cap.CapError):
+        p.admit(0, 1, cap.model_of(h), h.grid, 100, 5, h.start, buf, smooth=(0.0, 2))
+    p.close()
+    with pytest.raises(cap.CapError):
+        cap.Plan(16, 1.2, 0.02, 1, max_smooth_radius=17)
 
 
 def test_plan_errors(cap):
