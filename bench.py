@@ -141,6 +141,49 @@ def cpu_baseline(scene, max_seconds):
             "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
 
 
+def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
+    """The 64-human x 2^20-particle, K = 32, H = 200 scene: batched cycles
+    back to back and the rollout kernel's share of the ALU roofline."""
+    sc = scenes.config5()
+    humans = sc.humans
+    tracks = simulate(capred, torch, np, humans, cycles + 4)
+    shape = tune.shipped(humans) or {}
+    srv = make_server(capred, humans, shape, tracks)
+    try:
+        srv.step({h.hid: tracks[h.hid][1] for h in humans})
+        srv.drain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in range(1, 1 + cycles):
+            srv.step({h.hid: tracks[h.hid][c + 1] for h in humans})
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / cycles
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        durs = []
+        for _ in range(3):
+            srv.plan.replay_rollout(stream, e0, e1)
+            torch.cuda.synchronize()
+            durs.append(e0.elapsed_time(e1) * 1e-3)
+        roll = float(np.mean(durs))
+    finally:
+        srv.close()
+    psteps = sc.particle_steps
+    W = algorithmic_ops(humans[0].K, rates)
+    achieved = W * psteps / roll
+    return {"workload": "64 humans x 2^20 particles, 6 goals, 9 beta, K=32, v=1.2 m/s, "
+                        "dt=0.01 s, H=200, 512x512 grids at 0.02 m",
+            "particle_steps_per_cycle": psteps, "cycles": cycles,
+            "ms_per_cycle": round(sec * 1e3, 3), "value": float(f"{psteps / sec:.6e}"),
+            "tuning": shape,
+            "roofline": {"bound": "alu", "kernel": "plan_rollout_kernel",
+                         "ms_per_launch": round(roll * 1e3, 3),
+                         "ops_per_particle_step": round(W, 2),
+                         "achieved": round(achieved / 1e12, 3),
+                         "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
+                         "frac": round(achieved / PEAK_LANE_OPS, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,10 +195,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune even where the package's table holds this device and workload")
     ap.add_argument("--tuning", type=str, default=None,
                     help="JSON launch shape for the batched rollout (skips its autotuning)")
     ap.add_argument("--plain-tuning", type=str, default=None,
                     help="JSON launch shape for the plain launches (skips their autotuning)")
+    ap.add_argument("--largest-cycles", type=int, default=3,
+                    help="timed cycles of the 64-human x 2^20 scene (0 skips it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain copy of this many MiB (byte-counter calibration)")
     args = ap.parse_args()
@@ -192,11 +239,20 @@ def main():
     best = json.loads(args.tuning) if args.tuning else ({} if args.no_tune else None)
     best_plain = (json.loads(args.plain_tuning) if args.plain_tuning
                   else ({} if args.no_tune else None))
+    source = "flag"
+    if best is None and not args.retune:
+        best, source = tune.shipped(humans), "table"
     if best is None:
         best, _ = tune.autotune(humans, tracks, use_cache=False)
+        source = "autotune"
+    source_plain = "flag"
+    if best_plain is None and not args.retune:
+        best_plain, source_plain = tune.shipped(humans, plain=True), "table"
     if best_plain is None:
         best_plain, _ = tune.autotune(humans, tracks, plain=True, use_cache=False, cycles=3)
-    log(f"tuned batched: {best}  plain: {best_plain}")
+        source_plain = "autotune"
+    log(f"launch shape batched: {best} ({source})  plain: {best_plain} ({source_plain})  "
+        f"signatures {tune.signature(humans, False)} {tune.signature(humans, True)}")
 
     # ---------------------------------------------------------- batched, back-to-back
     srv = make_server(capred, humans, best, tracks)
@@ -267,6 +323,13 @@ def main():
     plain_value = psteps / plain_sec
     log(f"plain: {1e3 * plain_sec:.3f} ms/cycle, {plain_value:.3e} particle-steps/s")
 
+    largest = None
+    if args.largest_cycles > 0:
+        log("largest scene: 64 humans x 2^20 particles, K=32, H=200")
+        largest = largest_scene(capred, torch, np, tune, scenes, rates, args.largest_cycles)
+        log(f"  {largest['ms_per_cycle']} ms/cycle, {largest['value']:.3e} particle-steps/s, "
+            f"rollout frac {largest['roofline']['frac']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one full cycle)")
@@ -298,12 +361,14 @@ def main():
                                "K=16, v=1.2 m/s, dt=0.02 s, H=100, 256x256 grids at 0.05 m"
                                % sum(h.N for h in humans),
                    "particle_steps_per_cycle": psteps, "humans": len(humans),
-                   "tuning": best, "plain_tuning": best_plain},
+                   "tuning": best, "plain_tuning": best_plain,
+                   "tuning_source": [source, source_plain]},
         "latency": latency,
         "plain": {"value": float(f"{plain_value:.6e}"), "ms_per_step": round(plain_sec * 1e3, 4),
                   "batched_over_plain": round(value / plain_value, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "largest_scene": largest,
         "context": "paper: ~125 Hz for one human, n=8192, T=10, |U|=96 on an RTX 2080 Ti "
                    "(Tab. 1, JAX/XLA), about 1.0e7 particle-steps/s; different workload and hardware",
     }

@@ -94,3 +94,72 @@ def autotune(humans, tracks: Dict[int, np.ndarray], candidates: Optional[Sequenc
         except OSError:
             pass
     return best, table
+
+
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def shipped(humans, plain: bool = False) -> Optional[dict]:
+    """Launch shape recorded for this device and workload in the package's
+    table (written by ``python -m paper_2603_01122_amd.tune``), or None."""
+    try:
+        table = json.load(open(SHIPPED))
+    except (OSError, ValueError):
+        return None
+    entry = table.get(signature(humans, plain))
+    return dict(entry["best"]) if entry else None
+
+
+def main():
+    import argparse
+    from . import scenes
+    ap = argparse.ArgumentParser(
+        description="Tune the batched and plain launch shapes of a scene on this device and "
+                    "record them in the package's table.")
+    ap.add_argument("--scene", default="config3", help="scenes.<name>() workload")
+    ap.add_argument("--cycles", type=int, default=30, help="timed cycles per candidate")
+    ap.add_argument("--repeats", type=int, default=3, help="timings per candidate (min taken)")
+    ap.add_argument("--no-plain", action="store_true", help="tune the batched launch only")
+    args = ap.parse_args()
+    scene = getattr(scenes, args.scene)()
+    humans = scene.humans
+    T = 16 + args.repeats * (args.cycles + 3) * len(CANDIDATES)
+    h0 = humans[0]
+    _, pos = capred.simulate_tracks(
+        h0.K, h0.speed, h0.dt, h0.frame,
+        torch.tensor(np.array([h.start for h in humans]), dtype=torch.float64, device="cuda"),
+        torch.tensor(np.array([h.true_beta for h in humans], np.float32), device="cuda"),
+        torch.tensor(np.array([h.goals[h.true_goal] for h in humans], np.float32),
+                     device="cuda"),
+        T, seed=0, stream_id=0)
+    pos = pos.cpu().numpy()
+    tracks = {h.hid: pos[i] for i, h in enumerate(humans)}
+    try:
+        table = json.load(open(SHIPPED))
+    except (OSError, ValueError):
+        table = {}
+    for plain in ((False,) if args.no_plain else (False, True)):
+        times = {}
+        for _ in range(args.repeats):
+            for cand in CANDIDATES:
+                try:
+                    t = time_candidate(humans, tracks, cand, cycles=args.cycles, plain=plain)
+                except capred.CapError:
+                    continue
+                key = json.dumps(cand, sort_keys=True)
+                times[key] = min(times.get(key, float("inf")), t)
+        best = json.loads(min(times, key=times.get))
+        table[signature(humans, plain)] = {
+            "best": best, "scene": args.scene, "plain": plain,
+            "device": torch.cuda.get_device_name(0),
+            "ms_per_cycle": {k: round(v * 1e3, 4) for k, v in sorted(times.items())}}
+        print(f"{'plain' if plain else 'batched'}: best {best}", flush=True)
+        for k, v in sorted(times.items(), key=lambda kv: kv[1]):
+            print(f"  {k}: {v * 1e3:.4f} ms/cycle", flush=True)
+    with open(SHIPPED, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+        f.write("\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,141 @@
+"""The largest batched scene at full size: 64 humans x 2^20 particles, 6 goals,
+9 beta, K=32, dt=0.01 s, H=200, 512x512 grids at 0.02 m (about 1.3e10
+particle-steps per cycle), in one batched launch per cycle with the launch
+shape the package's tuning table records for it (the default shape if none).
+
+Checks, at that size:
+* posterior of every human within 1e-5 (log) of the oracle's;
+* counting invariant sum(counts[t]) + offgrid[t] = N for every human and step;
+* for two sampled humans, the single-human entry point reproduces the batched
+  grids bit for bit, and its per-particle traces agree with the oracle on a
+  sample of particles under the tie rule (first difference only at a heading
+  CDF tie within 1e-6, or a pair-CDF tie within 1e-5 since the GPU uses its
+  own posterior);
+* for one of them, the full grid stack equals the histogram rebuilt on the
+  host from the GPU's own 2^20 x 200 heading trace on the lattice (so every
+  binning path -- LDS windows and the direct-atomic fallback of wide steps --
+  is checked at full size);
+* probabilities equal count / N in IEEE FP32 on a sample of cells.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_01122_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+N_PRE = 2          # observed transitions (cycles) before the checked cycle
+SAMPLE = 16384     # particles replayed by the oracle per sampled human
+
+
+@pytest.fixture(scope="module")
+def cap():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_01122_amd import capred
+    return capred
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def replay_histogram(orc, h, z0, trace_k):
+    """Per-step histogram of lattice paths given their headings [N, H]."""
+    x0, y0, cell, nx, ny = h.grid
+    Sx, Sy = orc.lattice_steps(h.K, h.speed, h.dt, cell)
+    q = cell / 65536.0
+    X = np.full(trace_k.shape[0], np.rint((z0[0] - x0) / q), np.int64)
+    Y = np.full(trace_k.shape[0], np.rint((z0[1] - y0) / q), np.int64)
+    Sx, Sy = Sx.astype(np.int64), Sy.astype(np.int64)
+    counts = np.zeros((h.H, ny * nx), np.int64)
+    off = np.zeros(h.H, np.int64)
+    for t in range(h.H):
+        k = trace_k[:, t]
+        X += Sx[k]
+        Y += Sy[k]
+        cx, cy = X >> 16, Y >> 16
+        inside = (cx >= 0) & (cx < nx) & (cy >= 0) & (cy < ny)
+        counts[t] = np.bincount((cy[inside] * nx + cx[inside]), minlength=ny * nx)
+        off[t] = np.count_nonzero(~inside)
+    return counts.reshape(h.H, ny, nx), off
+
+
+def test_largest_scene_full_size(orc, cap):
+    from paper_2603_01122_amd import tune
+    from paper_2603_01122_amd.serve import HumanRequest, Server
+    sc = scenes.config5()
+    humans = sc.humans
+    tuning = tune.shipped(humans) or {}
+    tracks = {}
+    for h in humans:
+        _, pos = orc.simulate_tracks(K=h.K, speed=h.speed, dt=h.dt, frame=h.frame,
+                                     start=np.array([h.start]), beta=[h.true_beta],
+                                     goal=h.goals[h.true_goal][None], T=N_PRE, seed=0,
+                                     stream=h.hid)
+        tracks[h.hid] = pos[0]
+    h0 = humans[0]
+    note(f"config5: 64 humans x 2^20, K=32, H=200, 512x512, tuning {tuning}")
+    srv = Server(h0.K, h0.speed, h0.dt, len(humans), h0.H, 512, 512, 6, 9, tuning=tuning)
+    try:
+        for h in humans:
+            srv.submit(HumanRequest(h.hid, cap.model_of(h), h.grid, h.N, h.H, tracks[h.hid][0]))
+        for c in range(N_PRE):
+            srv.step({h.hid: tracks[h.hid][c + 1] for h in humans})
+        srv.drain()
+        torch.cuda.synchronize()
+        c = N_PRE - 1
+        note("posteriors and counting invariant, all humans")
+        for h in humans:
+            counts, probs, off, post = srv.grids(h.hid, c)
+            per_step = counts.view(h.H, -1).sum(dim=1, dtype=torch.int64) + off.to(torch.int64)
+            assert bool((per_step == h.N).all()), h.hid
+            _, b_o, _ = orc.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta,
+                                          goals=h.goals, obs=tracks[h.hid][:N_PRE + 1])
+            lb = np.log(post.cpu().numpy()).reshape(-1)
+            assert np.max(np.abs(lb - np.log(b_o.reshape(-1)))) <= 1e-5, h.hid
+
+        r = np.random.default_rng(5)
+        for n_h, h in enumerate((humans[0], humans[37])):
+            counts, probs, off, post = srv.grids(h.hid, c)
+            z0 = tuple(tracks[h.hid][N_PRE].astype(float))
+            note(f"single-human entry point, human {h.hid}, trace 2^20 x 200")
+            single = cap.predict_occupancy(cap.model_of(h), h.grid, z0, post.contiguous(), h.N,
+                                           h.H, seed=0, human_id=h.hid, cycle=c, trace=True)
+            torch.cuda.synchronize()
+            assert torch.equal(single["counts"], counts)
+            assert torch.equal(single["offgrid"], off)
+            tk = single["trace_k"].cpu().numpy()
+            tp = single["trace_pair"].cpu().numpy()
+            del single
+            idx = np.sort(r.choice(h.N, SAMPLE, replace=False))
+            _, b_o, _ = orc.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta,
+                                          goals=h.goals, obs=tracks[h.hid][:N_PRE + 1])
+            kw = dict(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals, grid=h.grid,
+                      z0=z0, belief=b_o.reshape(-1), N=h.N, H=h.H, seed=0, human=h.hid,
+                      cycle=c, idx=idx)
+            note(f"oracle tie check, {SAMPLE} sampled particles")
+            st, first = orc.tie_check(other_pair=tp[idx], other_k=tk[idx], window=1e-6,
+                                      pair_window=1e-5, **kw)
+            assert np.count_nonzero(st == 2) == 0
+            # each flagged particle moves at most 2 counts per step, so a
+            # flagged fraction <= 1e-3 keeps the occupancy TV within 1e-3
+            assert np.count_nonzero(st == 1) <= 1e-3 * SAMPLE
+            print(f"human {h.hid}: {np.count_nonzero(st == 1)} of {SAMPLE} sampled at ties")
+            cn = counts.cpu().numpy().view(np.uint32)
+            if n_h == 0:
+                note("host histogram of the GPU trace")
+                hc, ho = replay_histogram(orc, h, z0, tk)
+                assert np.array_equal(cn.astype(np.int64), hc)
+                assert np.array_equal(off.cpu().numpy().astype(np.int64), ho)
+            cells = r.integers(0, cn.size, 1 << 20)
+            nz = np.flatnonzero(cn.reshape(-1))
+            cells = np.concatenate([cells, nz[r.integers(0, nz.size, 1 << 16)]])
+            p = probs.cpu().numpy().reshape(-1)[cells]
+            assert np.array_equal(p, orc.normalize(cn.reshape(-1)[cells], h.N))
+    finally:
+        srv.close()
