@@ -141,6 +141,32 @@ def cpu_baseline(scene, max_seconds):
             "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
 
 
+def profiled_traffic(best):
+    """HBM bytes per rollout launch from the committed counter summary, if the
+    rollout's sources and the launch shape are those the counters were taken on."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "plan_rollout_kernel_16humans_counters.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "source_sha256",
+                                                 "sources", "tuning"))
+    if len(fields) != 4:
+        return None
+    h = hashlib.sha256()
+    for src in fields["sources"].split():
+        with open(os.path.join(here, src), "rb") as f:
+            h.update(f.read())
+    shape = "block_threads=%s particles_per_thread=%s" % (
+        best.get("block_threads"), best.get("particles_per_thread"))
+    if h.hexdigest() != fields["source_sha256"].strip() or shape != fields["tuning"].strip():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
     """The 64-human x 2^20-particle, K = 32, H = 200 scene: batched cycles
     back to back and the rollout kernel's share of the ALU roofline."""
@@ -160,6 +186,8 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
         sec = (time.perf_counter() - t0) / cycles
         stream = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)   # the library re-records both around the rollout launch
+        e1.record(stream)
         durs = []
         for _ in range(3):
             srv.plan.replay_rollout(stream, e0, e1)
@@ -184,6 +212,48 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
                          "frac": round(achieved / PEAK_LANE_OPS, 4)}}
 
 
+def tab1_latency(capred, torch, np, calls=50):
+    """One prediction at the shape of the paper's Tab. 1 (1 human, n = 8192,
+    50 x 50 grid at 0.1 m, 5 beta, 10 goals, 96 controls = 6 speeds x 16
+    headings, dt = 0.5 s) for T = 2..10: belief update with the newest
+    observation, rollout and normalisation, host to host (median of `calls`)."""
+    r = np.random.default_rng(2026)
+    speeds = np.array([0.25, 0.5, 0.75, 1.0, 1.25, 1.5])
+    goals = r.uniform(0.0, 5.0, (10, 2)).astype(np.float32)
+    beta = np.array([0.1, 0.5, 1.0, 5.0, 10.0], np.float32)
+    m = capred.Model(16, 0.0, 0.5, beta, goals, speeds=speeds)
+    grid = (0.0, 0.0, 0.1, 50, 50)
+    _, pos = capred.simulate_tracks(16, 0.0, 0.5, grid[:3],
+                                    torch.tensor([[2.5, 2.5]], dtype=torch.float64, device="cuda"),
+                                    torch.tensor([2.0], dtype=torch.float32, device="cuda"),
+                                    torch.tensor(goals[:1], device="cuda"), calls + 8,
+                                    seed=1, speeds=speeds)
+    obs = pos[0].contiguous()
+    pos_h = pos[0].cpu().numpy().astype(np.float64)
+    lb = capred.belief_reset(torch.empty((10, 5), dtype=torch.float64, device="cuda"))
+    b = torch.empty_like(lb)
+    out = {}
+    for T in (2, 4, 6, 8, 10):
+        counts = torch.empty((T, 50, 50), dtype=torch.int32, device="cuda")
+        off = torch.empty(T, dtype=torch.int32, device="cuda")
+        probs = torch.empty((T, 50, 50), dtype=torch.float32, device="cuda")
+        times = []
+        for i in range(calls + 3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            capred.belief_update(m, obs[i:i + 2], lb, b)
+            capred.predict_occupancy(m, grid, (pos_h[i + 1, 0], pos_h[i + 1, 1]), b,
+                                     8192, T, seed=0, cycle=i, counts=counts, offgrid=off)
+            capred.normalize(counts, 8192, probs)
+            torch.cuda.synchronize()
+            if i >= 3:
+                times.append(time.perf_counter() - t0)
+        out[f"T{T}_ms"] = round(float(np.median(times)) * 1e3, 4)
+    out["context"] = ("paper Tab. 1: 7-8 ms per prediction at T = 2..10 on an RTX 2080 Ti "
+                      "(JAX/XLA with JIT); different hardware")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +271,8 @@ def main():
                     help="JSON launch shape for the batched rollout (skips its autotuning)")
     ap.add_argument("--plain-tuning", type=str, default=None,
                     help="JSON launch shape for the plain launches (skips their autotuning)")
+    ap.add_argument("--no-tab1", action="store_true",
+                    help="skip the Tab. 1-shaped single-prediction latencies")
     ap.add_argument("--largest-cycles", type=int, default=3,
                     help="timed cycles of the 64-human x 2^20 scene (0 skips it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -288,7 +360,7 @@ def main():
     achieved = W * psteps / roll
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
-                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": profiled_traffic(best),
                 "kernel": "plan_rollout_kernel", "ms_per_launch": round(roll * 1e3, 4),
                 "ops_per_particle_step": round(W, 2),
                 "particle_steps_per_launch": psteps,
@@ -330,6 +402,12 @@ def main():
         log(f"  {largest['ms_per_cycle']} ms/cycle, {largest['value']:.3e} particle-steps/s, "
             f"rollout frac {largest['roofline']['frac']}")
 
+    tab1 = None
+    if not args.no_tab1:
+        log("Tab. 1-shaped latencies (n=8192, 50x50, 96 controls)")
+        tab1 = tab1_latency(capred, torch, np)
+        log(f"  {tab1}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one full cycle)")
@@ -369,6 +447,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "largest_scene": largest,
+        "tab1_shaped": tab1,
         "context": "paper: ~125 Hz for one human, n=8192, T=10, |U|=96 on an RTX 2080 Ti "
                    "(Tab. 1, JAX/XLA), about 1.0e7 particle-steps/s; different workload and hardware",
     }

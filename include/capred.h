@@ -13,7 +13,9 @@
  *     headings, and are emplaced per step on occupancy grids.
  *
  * Conventions shared by every call:
- *   headings      theta_k = 2 pi k / K, counter-clockwise from +x, fixed speed.
+ *   controls      headings theta_k = 2 pi k / K, counter-clockwise from +x, at one
+ *                 speed v, or S speeds x K headings with control u = s K + k
+ *                 (step v_s dt (cos, sin) theta_k); U = S K.
  *   pair index    j = g * B + b; beliefs are FP64 arrays laid out [G][B].
  *   lattice       prediction state is int32 on a lattice of pitch q = cell/2^16
  *                 from the grid origin; steps S_k = rint(v dt (cos,sin)theta_k / q);
@@ -22,9 +24,9 @@
  *   random draws  Philox4x32-10, key (seed lo, seed hi), uniform
  *                 u = (2 (w >> 9) + 1) 2^-24:
  *                   pair      counter (i, 0,       human, 2 cycle)     word 0
- *                   heading t counter (i, (t-1)/4, human, 2 cycle + 1) word (t-1)%4
+ *                   control t counter (i, (t-1)/4, human, 2 cycle + 1) word (t-1)%4
  *                   simulated track n, step t: counter (n, (t-1)/4, stream, 0xFFFFFFFF)
- *   inverse CDF   heading k = min{k : u C_{K-1} < C_k} (else K-1); pair j = min{j :
+ *   inverse CDF   control u = min{u : x C_{U-1} < C_u} (else U-1); pair j = min{j :
  *                 u < P_j} over the sequential FP64 prefix sums P (else the last
  *                 j with positive belief).
  *
@@ -51,6 +53,8 @@ extern "C" {
 #define CAP_MAX_B 16   /* rationality values per model             */
 #define CAP_MAX_G 64   /* goals per model                          */
 #define CAP_MAX_J 512  /* (beta, g) pairs, G * B                    */
+#define CAP_MAX_S 8    /* speeds of a multi-speed control set        */
+#define CAP_MAX_U 128  /* controls S * K                             */
 
 typedef enum cap_status {
   CAP_OK = 0,
@@ -64,12 +68,21 @@ typedef enum cap_status {
 /* Human model (Sec. III-A).  Host memory. */
 typedef struct cap_model {
   int32_t K;            /* headings, 2..CAP_MAX_K                                   */
-  double speed;         /* walking speed v in m/s, > 0                              */
+  double speed;         /* walking speed v in m/s, > 0 (used when n_speeds == 0)    */
   double dt;            /* prediction / observation step in s, > 0                  */
   int32_t B;            /* rationality values, 1..CAP_MAX_B                         */
   const float* beta;    /* host [B], every value > 0                                */
   int32_t G;            /* goals, 1..CAP_MAX_G, with G * B <= CAP_MAX_J             */
   const float* goals;   /* host [G][2], metres, world frame                         */
+  /* Multi-speed control set (the |U| = 96 experiments of Sec. IV, e.g. 6 speeds x
+   * 16 headings): n_speeds = 0 keeps the one speed above; 1..CAP_MAX_S uses
+   * speeds[s] (m/s, > 0) x K headings, S K <= CAP_MAX_U, and `speed` is ignored. */
+  int32_t n_speeds;
+  const double* speeds;  /* host [n_speeds]                                          */
+  /* Prediction-only mask of allowed speeds (bit s; 0 = all): the controls of the
+   * other speeds get Q = -inf, as for a human detected standing still
+   * (Sec. IV-B).  The belief update always uses every control. */
+  uint32_t speed_mask;
 } cap_model;
 
 /* Occupancy grid: nx * ny cells of side `cell` metres, lower-left corner at
@@ -87,12 +100,13 @@ int32_t cap_device_cu_count(void);
 
 /* ------------------------------------------------------------------------
  * Belief update, Eq. (beta_update) in log space (Sec. III-B):
- *   for each observed transition (z_t, z_{t+1}) the heading is recovered as
- *   k* = argmax_k <z_{t+1} - z_t, (cos, sin) theta_k> (lowest k on ties;
- *   a transition shorter than 1e-9 m is skipped), and
- *   log b(beta,g) += sum_t log pi(k*_t | z_t; beta, g),
+ *   for each observed transition (z_t, z_{t+1}) the control is recovered as the
+ *   nearest one: heading k* = argmax_k <z_{t+1} - z_t, (cos, sin) theta_k> (lowest k
+ *   on ties), speed s* = argmin_s |v_s dt - p| with p that projection (lowest s
+ *   on ties), u* = s* K + k*; a transition shorter than 1e-9 m is skipped; and
+ *   log b(beta,g) += sum_t log pi(u*_t | z_t; beta, g) over all U controls,
  *   followed by one log-sum-exp renormalisation over all (beta, g) in FP64.
- * The policy terms are FP32 (continuous steps fl32(v dt (cos,sin) theta_k)),
+ * The policy terms are FP32 (continuous steps fl32(v_s dt (cos,sin) theta_k)),
  * accumulated in FP64.
  *   obs_dev         [n_obs + 1][2] FP32 metres, n_obs >= 0
  *   log_belief_dev  [G][B] FP64, in: prior (log), out: posterior (log);
@@ -109,11 +123,12 @@ cap_status cap_belief_reset(int32_t G, int32_t B, double* log_belief_dev, void* 
 /* ------------------------------------------------------------------------
  * Alg. 1 for one human: N particles start at z0 (host, metres), each draws
  * (beta, g) from belief_dev once (bootstrapped belief, Sec. III-B) and takes H
- * Boltzmann heading steps; grid t receives the particles after t steps.
+ * Boltzmann control steps over the allowed controls (model->speed_mask); grid t
+ * receives the particles after t steps.
  *   belief_dev   [G][B] FP64, non-negative, summing to 1 (not renormalised).
  *   counts_dev   [H][ny][nx] uint32 out; zeroed by the call.
  *   offgrid_dev  [H] uint32 out (particles outside the grid), zeroed; may be NULL.
- *   trace_k_dev  [N][H] uint8 out, chosen heading per step; may be NULL.
+ *   trace_k_dev  [N][H] uint8 out, chosen control u per step; may be NULL.
  *   trace_pair_dev [N] int32 out, pair index j per particle; may be NULL.
  *   1 <= N <= 2^30, 1 <= H <= 4096, cycle < 2^31 - 1.
  * Errors: CAP_E_INVALID for a bad model/grid/size, a start or goal whose
@@ -166,11 +181,13 @@ cap_status cap_philox_blocks(int64_t n, uint32_t c0, uint32_t c1, uint32_t c2, u
 /* ------------------------------------------------------------------------
  * Synthetic humans: n tracks of T lattice steps, each following the Boltzmann
  * policy with its own fixed (beta, goal) (the model of Sec. III-A, used as a
- * simulator).  The lattice frame (x0, y0, cell) fixes q.
+ * simulator) over the control set of (K, speed) or (n_speeds, speeds) as in
+ * cap_model (every control allowed).  The lattice frame (x0, y0, cell) fixes q.
  *   start_dev [n][2] FP64 metres, beta_dev [n] FP32, goal_dev [n][2] FP32 metres.
  *   lat_dev   [n][T+1][2] int32 lattice positions out (may be NULL).
  *   pos_dev   [n][T+1][2] FP32 metres out: fl32(origin + X q) (may be NULL). */
-cap_status cap_simulate_tracks(int32_t K, double speed, double dt, double x0, double y0,
+cap_status cap_simulate_tracks(int32_t K, double speed, int32_t n_speeds, const double* speeds,
+                               double dt, double x0, double y0,
                                double cell, int32_t n, int32_t T, const double* start_dev,
                                const float* beta_dev, const float* goal_dev, uint64_t seed,
                                uint32_t stream_id, int32_t* lat_dev, float* pos_dev,
@@ -236,6 +253,8 @@ typedef struct cap_plan_config {
   int32_t grid_blocks;          /* 0 = default; persistent blocks per launch    */
   int32_t max_smooth_radius;    /* 0 = no smoothing stage; 1..16 = largest radius a
                                    slot may ask for (sizes the stage's LDS tile) */
+  int32_t n_speeds;             /* shared control set as in cap_model: 0 = one speed */
+  double speeds[CAP_MAX_S];     /* m/s, first n_speeds entries                   */
 } cap_plan_config;
 
 #define CAP_MAX_SLOTS 256
@@ -259,6 +278,7 @@ typedef struct cap_slot_desc {
                                    are the Gaussian-smoothed occupancy of
                                    cap_smooth_occupancy (requires probs_dev)       */
   double smooth_sigma;          /* kernel width in cells, > 0 when smooth_radius > 0 */
+  uint32_t speed_mask;          /* allowed speeds of the prediction (bit s; 0 = all) */
 } cap_slot_desc;
 
 cap_status cap_plan_create(const cap_plan_config* cfg, cap_plan** out);
@@ -267,6 +287,13 @@ void cap_plan_destroy(cap_plan* plan);
 cap_status cap_plan_set_slot(cap_plan* plan, int32_t slot, const cap_slot_desc* desc);
 /* Retire the human in `slot`; its buffers are not touched by later cycles. */
 cap_status cap_plan_clear_slot(cap_plan* plan, int32_t slot);
+/* From the next cycle on, predict `slot` with the allowed speeds `mask` (bit s;
+ * 0 = all): a human detected standing still gets only the slow controls
+ * (Q = -inf for the others, Sec. IV-B).  Errors: no allowed speed. */
+cap_status cap_plan_set_speed_mask(cap_plan* plan, int32_t slot, uint32_t mask);
+/* Re-uniformise the belief of `slot` before the next cycle's update, as after
+ * the human leaves a goal (Sec. IV-B). */
+cap_status cap_plan_reset_belief(cap_plan* plan, int32_t slot);
 /* Stage the new observed positions of `slot` for the next cycle:
  * xy [n_new][2] FP32 metres (host), 0 <= n_new <= max_obs.  The first one
  * continues from the slot's last observed position. */

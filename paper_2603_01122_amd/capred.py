@@ -36,10 +36,14 @@ class CapError(RuntimeError):
         self.status = status
 
 
+CAP_MAX_S = 8
+
+
 class cap_model(C.Structure):
     _fields_ = [("K", C.c_int32), ("speed", C.c_double), ("dt", C.c_double), ("B", C.c_int32),
                 ("beta", C.POINTER(C.c_float)), ("G", C.c_int32),
-                ("goals", C.POINTER(C.c_float))]
+                ("goals", C.POINTER(C.c_float)), ("n_speeds", C.c_int32),
+                ("speeds", C.POINTER(C.c_double)), ("speed_mask", C.c_uint32)]
 
 
 class cap_grid(C.Structure):
@@ -52,7 +56,8 @@ class cap_plan_config(C.Structure):
                 ("dt", C.c_double), ("max_obs", C.c_int32), ("ring", C.c_int32),
                 ("block_threads", C.c_int32), ("particles_per_thread", C.c_int32),
                 ("lds_bytes", C.c_int32), ("grid_blocks", C.c_int32),
-                ("max_smooth_radius", C.c_int32)]
+                ("max_smooth_radius", C.c_int32), ("n_speeds", C.c_int32),
+                ("speeds", C.c_double * CAP_MAX_S)]
 
 
 class cap_slot_desc(C.Structure):
@@ -63,7 +68,7 @@ class cap_slot_desc(C.Structure):
                 ("offgrid_dev", C.c_void_p), ("probs_dev", C.c_void_p),
                 ("log_belief_dev", C.c_void_p), ("belief_dev", C.c_void_p),
                 ("reset_belief", C.c_int32), ("smooth_radius", C.c_int32),
-                ("smooth_sigma", C.c_double)]
+                ("smooth_sigma", C.c_double), ("speed_mask", C.c_uint32)]
 
 
 _vp, _i32, _u32, _u64, _i64, _d, _sz = (C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64,
@@ -87,8 +92,8 @@ _sig("cap_predict_occupancy", _i32, C.POINTER(cap_model), C.POINTER(cap_grid),
 _sig("cap_normalize", _i32, _vp, _i64, _i32, _vp, _vp)
 _sig("cap_smooth_occupancy", _i32, _vp, _i32, _i32, _i32, _i32, C.c_double, _i32, _vp, _vp)
 _sig("cap_union_max", _i32, C.POINTER(_vp), _i32, _i64, _vp, _vp)
-_sig("cap_simulate_tracks", _i32, _i32, _d, _d, _d, _d, _d, _i32, _i32, _vp, _vp, _vp, _u64, _u32,
-     _vp, _vp, _vp)
+_sig("cap_simulate_tracks", _i32, _i32, _d, _i32, C.POINTER(C.c_double), _d, _d, _d, _d, _i32,
+     _i32, _vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp)
 _sig("cap_loglik", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp)
 _sig("cap_loglik_backward", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _i32,
      _vp, _vp, _vp, _vp, _sz, _vp)
@@ -105,6 +110,8 @@ if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_destroy", None, _vp)
     _sig("cap_plan_set_slot", _i32, _vp, _i32, C.POINTER(cap_slot_desc))
     _sig("cap_plan_clear_slot", _i32, _vp, _i32)
+    _sig("cap_plan_set_speed_mask", _i32, _vp, _i32, _u32)
+    _sig("cap_plan_reset_belief", _i32, _vp, _i32)
     _sig("cap_plan_stage_obs", _i32, _vp, _i32, C.POINTER(C.c_float), _i32)
     _sig("cap_plan_run", _i32, _vp, _u64, _u32, _vp)
     _sig("cap_plan_run_plain", _i32, _vp, _u64, _u32, _vp)
@@ -114,7 +121,8 @@ if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_replay_rollout", _i32, _vp, _vp, _vp, _vp)
     EXPORTED += ["cap_plan_replay_rollout", "cap_plan_create", "cap_plan_destroy", "cap_plan_set_slot",
                  "cap_plan_clear_slot", "cap_plan_stage_obs", "cap_plan_run",
-                 "cap_plan_run_plain", "cap_plan_sync", "cap_plan_stats", "cap_plan_tuning"]
+                 "cap_plan_run_plain", "cap_plan_sync", "cap_plan_stats", "cap_plan_tuning",
+                 "cap_plan_set_speed_mask", "cap_plan_reset_belief"]
 
 
 def _check(rc: int, what: str):
@@ -145,16 +153,22 @@ def _ptr(t: Optional[torch.Tensor], dtype: torch.dtype, name: str, shape=None) -
 
 @dataclasses.dataclass
 class Model:
-    """Human model of Sec. III-A: K headings at speed v, step dt, beta grid, goals."""
+    """Human model of Sec. III-A: K headings at speed v (or at each of `speeds`,
+    controls u = s K + k), step dt, beta grid, goals; speed_mask (bit s, 0 = all)
+    restricts the prediction to some speeds."""
     K: int
     speed: float
     dt: float
     beta: np.ndarray     # float32 [B]
     goals: np.ndarray    # float32 [G, 2] metres
+    speeds: Optional[np.ndarray] = None   # float64 [S] m/s, or None for the one speed
+    speed_mask: int = 0
 
     def __post_init__(self):
         self.beta = np.ascontiguousarray(self.beta, np.float32).reshape(-1)
         self.goals = np.ascontiguousarray(self.goals, np.float32).reshape(-1, 2)
+        if self.speeds is not None:
+            self.speeds = np.ascontiguousarray(self.speeds, np.float64).reshape(-1)
 
     @property
     def B(self):
@@ -164,10 +178,23 @@ class Model:
     def G(self):
         return int(self.goals.shape[0])
 
+    @property
+    def S(self):
+        return 1 if self.speeds is None else int(self.speeds.size)
+
+    @property
+    def U(self):
+        return self.K * self.S
+
     def c(self) -> cap_model:
-        return cap_model(self.K, float(self.speed), float(self.dt), self.B,
-                         self.beta.ctypes.data_as(C.POINTER(C.c_float)), self.G,
-                         self.goals.ctypes.data_as(C.POINTER(C.c_float)))
+        m = cap_model(self.K, float(self.speed), float(self.dt), self.B,
+                      self.beta.ctypes.data_as(C.POINTER(C.c_float)), self.G,
+                      self.goals.ctypes.data_as(C.POINTER(C.c_float)))
+        if self.speeds is not None:
+            m.n_speeds = self.speeds.size
+            m.speeds = self.speeds.ctypes.data_as(C.POINTER(C.c_double))
+        m.speed_mask = int(self.speed_mask)
+        return m
 
 
 def model_of(h) -> Model:
@@ -300,14 +327,18 @@ def copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
 
 def simulate_tracks(K: int, speed: float, dt: float, frame: Sequence[float],
                     start: torch.Tensor, beta: torch.Tensor, goal: torch.Tensor, T: int,
-                    seed: int = 0, stream_id: int = 0, stream=None):
-    """Synthetic humans.  start [n,2] f64, beta [n] f32, goal [n,2] f32 (device).
+                    seed: int = 0, stream_id: int = 0, stream=None, speeds=None):
+    """Synthetic humans.  start [n,2] f64, beta [n] f32, goal [n,2] f32 (device);
+    speeds (host, m/s) selects the multi-speed control set.
     Returns (lattice [n,T+1,2] int32, positions [n,T+1,2] f32)."""
     n = start.shape[0]
     lat = torch.empty((n, T + 1, 2), dtype=torch.int32, device=start.device)
     pos = torch.empty((n, T + 1, 2), dtype=torch.float32, device=start.device)
     x0, y0, cell = frame
-    _check(_lib.cap_simulate_tracks(K, speed, dt, x0, y0, cell, n, T,
+    v = None if speeds is None else np.ascontiguousarray(speeds, np.float64).reshape(-1)
+    _check(_lib.cap_simulate_tracks(K, speed, 0 if v is None else v.size,
+                                    None if v is None else v.ctypes.data_as(C.POINTER(C.c_double)),
+                                    dt, x0, y0, cell, n, T,
                                     _ptr(start, torch.float64, "start", (n, 2)),
                                     _ptr(beta, torch.float32, "beta", (n,)),
                                     _ptr(goal, torch.float32, "goal", (n, 2)), seed, stream_id,
@@ -402,13 +433,22 @@ class Plan:
 
     def __init__(self, K: int, speed: float, dt: float, n_slots: int, max_obs: int = 1,
                  ring: int = 2, block_threads: int = 0, particles_per_thread: int = 0,
-                 lds_bytes: int = 0, grid_blocks: int = 0, max_smooth_radius: int = 0):
+                 lds_bytes: int = 0, grid_blocks: int = 0, max_smooth_radius: int = 0,
+                 speeds=None):
         cfg = cap_plan_config(n_slots, K, speed, dt, max_obs, ring, block_threads,
                               particles_per_thread, lds_bytes, grid_blocks, max_smooth_radius)
+        if speeds is not None:
+            v = np.ascontiguousarray(speeds, np.float64).reshape(-1)
+            if v.size > CAP_MAX_S:
+                raise ValueError(f"at most {CAP_MAX_S} speeds")
+            cfg.n_speeds = v.size
+            for i, x in enumerate(v):
+                cfg.speeds[i] = float(x)
         h = C.c_void_p()
         _check(_lib.cap_plan_create(C.byref(cfg), C.byref(h)), "cap_plan_create")
         self._h = h
         self.K, self.speed, self.dt, self.ring = K, speed, dt, ring
+        self.speeds = None if speeds is None else np.asarray(speeds, np.float64).reshape(-1)
         self.n_slots = n_slots
         self.buffers = {}
 
@@ -426,7 +466,9 @@ class Plan:
     def tuning(self) -> dict:
         c = cap_plan_config()
         _check(_lib.cap_plan_tuning(self._h, C.byref(c)), "cap_plan_tuning")
-        return {f: getattr(c, f) for f, _ in cap_plan_config._fields_}
+        out = {f: getattr(c, f) for f, _ in cap_plan_config._fields_}
+        out["speeds"] = list(out["speeds"])[:c.n_speeds]
+        return out
 
     def admit(self, slot: int, human_id: int, model: Model, grid, N: int, H: int,
               last_xy, buffers: SlotBuffers, reset_belief: bool = True,
@@ -434,6 +476,9 @@ class Plan:
         """smooth = (sigma, radius) in cells asks for Gaussian-smoothed probabilities."""
         if model.K != self.K:
             raise ValueError("model K differs from the plan's")
+        if (model.speeds is None) != (self.speeds is None) or (
+                model.speeds is not None and not np.array_equal(model.speeds, self.speeds)):
+            raise ValueError("model speeds differ from the plan's control set")
         desc = cap_slot_desc()
         desc.human_id = human_id
         desc.N, desc.H, desc.B, desc.G = N, H, model.B, model.G
@@ -452,12 +497,19 @@ class Plan:
         desc.reset_belief = 1 if reset_belief else 0
         if smooth is not None:
             desc.smooth_sigma, desc.smooth_radius = float(smooth[0]), int(smooth[1])
+        desc.speed_mask = int(model.speed_mask)
         _check(_lib.cap_plan_set_slot(self._h, slot, C.byref(desc)), "cap_plan_set_slot")
         self.buffers[slot] = buffers
 
     def retire(self, slot: int):
         _check(_lib.cap_plan_clear_slot(self._h, slot), "cap_plan_clear_slot")
         self.buffers.pop(slot, None)
+
+    def set_speed_mask(self, slot: int, mask: int):
+        _check(_lib.cap_plan_set_speed_mask(self._h, slot, int(mask)), "cap_plan_set_speed_mask")
+
+    def reset_belief(self, slot: int):
+        _check(_lib.cap_plan_reset_belief(self._h, slot), "cap_plan_reset_belief")
 
     def stage(self, slot: int, xy):
         a = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)

@@ -22,13 +22,14 @@ using namespace capred;
 extern "C" cap_status cap_belief_update(const cap_model* model, const float* obs_dev,
                                         int32_t n_obs, double* log_belief_dev,
                                         double* belief_dev, void* stream) {
-  cap_status st = check_model(model);
+  Controls c;
+  cap_status st = check_model(model, &c);
   if (st != CAP_OK) return st;
   if (n_obs < 0) return fail(CAP_E_INVALID, "n_obs must be >= 0");
   if (!log_belief_dev) return fail(CAP_E_INVALID, "log_belief is NULL");
   if (n_obs > 0 && !obs_dev) return fail(CAP_E_INVALID, "obs is NULL");
-  const BeliefModel m = make_belief_model(model->K, model->speed, model->dt, model->B,
-                                          model->beta, model->G, model->goals);
+  const BeliefModel m = make_belief_model(c, model->dt, model->B, model->beta, model->G,
+                                          model->goals);
   hipLaunchKernelGGL(belief_update_kernel, dim3(1), dim3(kBeliefThreads), 0, as_stream(stream),
                      m, obs_dev, n_obs, log_belief_dev, belief_dev);
   CAP_HIP(hipGetLastError());

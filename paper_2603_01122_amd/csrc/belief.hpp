@@ -14,9 +14,11 @@ struct BeliefShared {
   double red[kBeliefThreads / 64];
 };
 
-// Heading recovered from one observed transition: argmax_k <dz, (cos, sin)theta_k>
-// with the lowest k on ties; -1 when the displacement is below 1e-9 m.
-__device__ __forceinline__ int recover_heading(const BeliefModel& m, float dx, float dy) {
+// Control recovered from one observed transition (the nearest control):
+// heading k* = argmax_k <dz, (cos, sin)theta_k> with the lowest k on ties, then
+// the speed whose step v_s dt is nearest to that projection (lowest s on
+// ties); returns u* = s* K + k*, or -1 when the displacement is below 1e-9 m.
+__device__ __forceinline__ int recover_control(const BeliefModel& m, float dx, float dy) {
   if (fmaf(dx, dx, dy * dy) < 1e-18f) return -1;
   int ks = 0;
   float best = -INFINITY;
@@ -27,13 +29,24 @@ __device__ __forceinline__ int recover_heading(const BeliefModel& m, float dx, f
       ks = k;
     }
   }
-  return ks;
+  int ss = 0;
+  float err = INFINITY;
+  for (int s = 0; s < m.S; ++s) {
+    const float e = fabsf(m.vdt[s] - best);
+    if (e < err) {
+      err = e;
+      ss = s;
+    }
+  }
+  return ss * m.K + ks;
 }
 
-// log pi(k* | z; beta_b, g) for every b, FP32.  Delta_k = |a + s_k| - |a| with
-// a = z - g carried as an unevaluated sum (hi + lo, exact subtraction), from
-// the cancellation-free quotient (2 a.s_k + |s_k|^2) / (|a + s_k| + |a|); then
-// l_k = -beta Delta_k and log pi = l_{k*} - max l - log sum exp(l - max l).
+// log pi(u* | z; beta_b, g) for every b over the U controls, FP32.
+// Delta_u = |a + s_u| - |a| with a = z - g carried as an unevaluated sum
+// (hi + lo, exact subtraction), from the cancellation-free quotient
+// (2 a.s_u + |s_u|^2) / (|a + s_u| + |a|); then l_u = -beta Delta_u and
+// log pi = l_{u*} - max l - log sum exp(l - max l).  NMAX bounds U.
+template <int NMAX>
 __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, float zy, int ks,
                                              float gx, float gy, const float* beta, int B,
                                              float* out) {
@@ -41,6 +54,7 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
     for (int b = 0; b < B; ++b) out[b] = 0.f;
     return;
   }
+  const int U = m.U;
   const float ax = zx - gx, bx = ax - zx;
   const float ax_lo = (zx - (ax - bx)) + (-gx - bx);
   const float ay = zy - gy, by = ay - zy;
@@ -48,8 +62,8 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
   const float D2 = fmaf(ax, ax, ay * ay);
   const float D = sqrtf(D2);
   const float ax2 = ax + ax, ay2 = ay + ay;
-  float dl[CAP_MAX_K];
-  for (int k = 0; k < m.K; ++k) {
+  float dl[NMAX];
+  for (int k = 0; k < U; ++k) {
     const float corr = fmaf(2.f * ax_lo, m.sx[k], fmaf(2.f * ay_lo, m.sy[k], m.s2[k]));
     const float n = fmaf(ax2, m.sx[k], fmaf(ay2, m.sy[k], corr));
     const float d = sqrtf(fmaxf(D2 + n, 0.f));
@@ -58,9 +72,9 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
   for (int b = 0; b < B; ++b) {
     const float nbt = -beta[b];
     float mx = -INFINITY;
-    for (int k = 0; k < m.K; ++k) mx = fmaxf(mx, nbt * dl[k]);
+    for (int k = 0; k < U; ++k) mx = fmaxf(mx, nbt * dl[k]);
     float s = 0.f;
-    for (int k = 0; k < m.K; ++k) s += expf(nbt * dl[k] - mx);
+    for (int k = 0; k < U; ++k) s += expf(nbt * dl[k] - mx);
     out[b] = (nbt * dl[ks] - mx) - logf(s);
   }
 }
@@ -98,9 +112,9 @@ __device__ void belief_update_block(const BeliefModel& m, const float* __restric
     for (int item = tid; item < nt * J; item += nthr) {
       const int tl = item / J, j = item - tl * J, g = j / B, b = j - g * B, t = t0 + tl;
       const float zx = obs[2 * t], zy = obs[2 * t + 1];
-      const int ks = recover_heading(m, obs[2 * t + 2] - zx, obs[2 * t + 3] - zy);
+      const int ks = recover_control(m, obs[2 * t + 2] - zx, obs[2 * t + 3] - zy);
       float term;
-      policy_terms(m, zx, zy, ks, m.gx[g], m.gy[g], m.beta + b, 1, &term);
+      policy_terms<CAP_MAX_U>(m, zx, zy, ks, m.gx[g], m.gy[g], m.beta + b, 1, &term);
       sh.ell[tl * J + j] = term;
     }
     __syncthreads();

@@ -106,12 +106,13 @@ __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sq
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// Per-model heading constants for the lattice rollout, in lattice units:
-// step (fx, fy) and its squared length s2 (all FP32).
+// Per-model control constants for the lattice rollout, in lattice units:
+// step (fx, fy) of control u = s K + k (integers, exact in FP32) and its
+// squared length s2 (FP32).
 struct HeadingTable {
-  float fx[CAP_MAX_K];
-  float fy[CAP_MAX_K];
-  float s2[CAP_MAX_K];
+  float fx[CAP_MAX_U];
+  float fy[CAP_MAX_U];
+  float s2[CAP_MAX_U];
 };
 
 // Inverse CDF over K non-decreasing prefix sums: #{k < K-1 : C_k <= thr},
@@ -227,6 +228,89 @@ __device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float 
     }
     return cdf_index<KT>(C, u * acc, Krt);
   }
+}
+
+// Multi-speed draw: the inverse CDF over all U = S KT controls (u = s KT + k,
+// prefix sums in u order) in two passes.  Pass 1 accumulates the weights of
+// every allowed speed block in u order and keeps the running sum at the end of
+// each block; the speed block s* = min{s : x < sum_s} (x = u C_{U-1}, capped at
+// the last allowed speed) follows from those S sums.  Pass 2 recomputes block
+// s* from the same constants (LDS copy `ctl`, per-lane index) starting from the
+// sum before it, so its prefix sums are bit-identical to the flat sequence,
+// and the heading is cdf_index over them.  Blocks of masked speeds add nothing
+// (weight 0, Q = -inf).  Requires a point-symmetric table per speed.
+template <int KT, bool SHIFT>
+__device__ __forceinline__ int draw_control(float ax, float ay, float ib, float u,
+                                            const HeadingTable& T, int S, uint32_t smask,
+                                            int s_last, const float4* ctl) {
+  static_assert(KT >= 4 && (KT & (KT - 1)) == 0, "multi-speed draw needs a power-of-two K");
+  constexpr int KH = KT / 2;
+  const float D2 = fmaf(ax, ax, ay * ay);
+  const float D = fast_sqrt(D2);
+  const float Dib = D * ib;
+  const float ax2 = ax + ax, ay2 = ay + ay;
+  float m = 0.f;
+  if constexpr (SHIFT) {
+    m = -INFINITY;
+#pragma unroll
+    for (int s = 0; s < CAP_MAX_S; ++s) {
+      if (s >= S) break;
+      if (!((smask >> s) & 1u)) continue;
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int c = s * KT + k;
+        const float dot = fmaf(ax2, T.fx[c], ay2 * T.fy[c]);
+        const float np = T.s2[c] + dot, nm = T.s2[c] - dot;
+        const float dp = fast_sqrt(fabsf(D2 + np)), dm = fast_sqrt(fabsf(D2 + nm));
+        m = fmaxf(m, fmaxf(np * fast_rcp(fmaf(dp, ib, Dib)), nm * fast_rcp(fmaf(dm, ib, Dib))));
+      }
+    }
+  }
+  float bs[CAP_MAX_S];
+  float acc = 0.f;
+#pragma unroll
+  for (int s = 0; s < CAP_MAX_S; ++s) {
+    if (s < S && ((smask >> s) & 1u)) {
+      float e[KT];
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int c = s * KT + k;
+        const float dot = fmaf(ax2, T.fx[c], ay2 * T.fy[c]);
+        const float np = T.s2[c] + dot, nm = T.s2[c] - dot;
+        const float dp = fast_sqrt(fabsf(D2 + np)), dm = fast_sqrt(fabsf(D2 + nm));
+        e[k] = np * fast_rcp(fmaf(dp, ib, Dib));
+        e[k + KH] = nm * fast_rcp(fmaf(dm, ib, Dib));
+      }
+#pragma unroll
+      for (int k = 0; k < KT; ++k) acc += fast_exp2(SHIFT ? e[k] - m : e[k]);
+    }
+    bs[s] = acc;
+  }
+  const float thr = u * acc;
+  int ss = 0;
+#pragma unroll
+  for (int s = 0; s < CAP_MAX_S - 1; ++s) ss += (s < s_last && bs[s] <= thr) ? 1 : 0;
+  float base = 0.f;
+#pragma unroll
+  for (int s = 0; s < CAP_MAX_S - 1; ++s) base = (s == ss - 1) ? bs[s] : base;
+  float C[KT];
+  const float4* cb = ctl + ss * KT;
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    const float4 c = cb[k];
+    const float dot = fmaf(ax2, c.x, ay2 * c.y);
+    const float np = c.z + dot, nm = c.z - dot;
+    const float dp = fast_sqrt(fabsf(D2 + np)), dm = fast_sqrt(fabsf(D2 + nm));
+    C[k] = np * fast_rcp(fmaf(dp, ib, Dib));
+    C[k + KH] = nm * fast_rcp(fmaf(dm, ib, Dib));
+  }
+  float a2 = base;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    a2 += fast_exp2(SHIFT ? C[k] - m : C[k]);
+    C[k] = a2;
+  }
+  return ss * KT + cdf_index<KT>(C, thr, KT);
 }
 
 }  // namespace capred

@@ -45,8 +45,8 @@ __global__ void __launch_bounds__(kLLThreads) loglik_kernel(const LLArgs a, doub
   for (int b = 0; b < a.B; ++b) acc[b] = 0.0;
   for (int t = lane; t < len; t += 64) {
     const float zx = z[2 * t], zy = z[2 * t + 1];
-    const int ks = recover_heading(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
-    policy_terms(a.m, zx, zy, ks, gx, gy, beta, a.B, terms);
+    const int ks = recover_control(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
+    policy_terms<CAP_MAX_K>(a.m, zx, zy, ks, gx, gy, beta, a.B, terms);
     for (int b = 0; b < a.B; ++b) acc[b] += (double)terms[b];
   }
   for (int b = 0; b < a.B; ++b) {
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kLLThreads)
   float dl[CAP_MAX_K], dk[CAP_MAX_K];
   for (int t = lane; t < len; t += 64) {
     const float zx = z[2 * t], zy = z[2 * t + 1];
-    const int ks = recover_heading(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
+    const int ks = recover_control(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
     if (ks < 0) continue;
     const float ax = zx - gx, bx = ax - zx;
     const float ax_lo = (zx - (ax - bx)) + (-gx - bx);
@@ -172,14 +172,15 @@ static cap_status make_ll_args(int32_t K, double speed, double dt, const float* 
                                const int32_t* lengths, int32_t N, int32_t Tmax,
                                const float* goals, int32_t G, const float* log_beta, int32_t B,
                                int32_t per_track, LLArgs* a) {
-  cap_status st = check_model_shape(K, speed, dt);
+  Controls c;
+  cap_status st = make_controls(K, speed, dt, 0, nullptr, 0u, &c);
   if (st != CAP_OK) return st;
   if (N < 0 || Tmax < 0) return fail(CAP_E_INVALID, "N and Tmax must be >= 0");
   if (G < 1 || G > CAP_MAX_G || B < 1 || B > CAP_MAX_B)
     return fail(CAP_E_INVALID, "G in [1, 64] and B in [1, 16] required");
   if (N > 0 && (!tracks || !lengths || !goals || !log_beta))
     return fail(CAP_E_INVALID, "tracks/lengths/goals/log_beta is NULL");
-  a->m = make_belief_model(K, speed, dt, 0, nullptr, 0, nullptr);
+  a->m = make_belief_model(c, dt, 0, nullptr, 0, nullptr);
   a->tracks = tracks;
   a->lengths = lengths;
   a->N = N;

@@ -192,10 +192,11 @@ __device__ __forceinline__ int slot_of_tile(const CycleHeader* H, int tile) {
   return lo;
 }
 
-template <int KT, int P, bool SHIFT>
+template <int KT, int P, bool SHIFT, bool MS>
 __global__ void __launch_bounds__(1024)
     plan_rollout_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int cap) {
   __shared__ TileShared sh;
+  __shared__ float4 ctl[MS ? CAP_MAX_U : 1];
   __shared__ int s_tile;
   extern __shared__ uint32_t win[];
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
@@ -223,20 +224,22 @@ __global__ void __launch_bounds__(1024)
     const int64_t first = (int64_t)(tile - H->tile_begin[s]) * H->per_tile;
     // rollout_tile starts and ends with a barrier: s_tile is not rewritten
     // before every thread has read it.
-    rollout_tile<KT, P, SHIFT>(sl[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap);
+    rollout_tile<KT, P, SHIFT, MS>(sl[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap, ctl);
   }
 }
 
 // One human's tiles, one block per tile (the per-human reference launch).
-template <int KT, int P, bool SHIFT>
+template <int KT, int P, bool SHIFT, bool MS>
 __global__ void __launch_bounds__(1024)
     plan_rollout_one_kernel(const uint8_t* __restrict__ base, int s, int cap) {
   __shared__ TileShared sh;
+  __shared__ float4 ctl[MS ? CAP_MAX_U : 1];
   extern __shared__ uint32_t win[];
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
   for (int i = threadIdx.x; i < 2 * cap; i += blockDim.x) win[i] = 0u;
   const int64_t first = (int64_t)blockIdx.x * H->per_tile;
-  rollout_tile<KT, P, SHIFT>(slots_of(base)[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap);
+  rollout_tile<KT, P, SHIFT, MS>(slots_of(base)[s].rd, first, H->seed_lo, H->seed_hi, sh, win,
+                                 cap, ctl);
 }
 
 // ---------------------------------------------------------------- host
@@ -295,30 +298,42 @@ struct cap_plan {
 
 namespace capred {
 
-template <int KT, int P>
+template <int KT, int P, bool MS>
 static void pick_fns_p(const void** r, const void** one) {
-  r[0] = (const void*)plan_rollout_kernel<KT, P, false>;
-  r[1] = (const void*)plan_rollout_kernel<KT, P, true>;
-  one[0] = (const void*)plan_rollout_one_kernel<KT, P, false>;
-  one[1] = (const void*)plan_rollout_one_kernel<KT, P, true>;
+  r[0] = (const void*)plan_rollout_kernel<KT, P, false, MS>;
+  r[1] = (const void*)plan_rollout_kernel<KT, P, true, MS>;
+  one[0] = (const void*)plan_rollout_one_kernel<KT, P, false, MS>;
+  one[1] = (const void*)plan_rollout_one_kernel<KT, P, true, MS>;
 }
 
-template <int KT>
+template <int KT, bool MS>
 static void pick_fns(int P, const void** r, const void** one) {
   switch (P) {
-    case 1: pick_fns_p<KT, 1>(r, one); break;
-    case 2: pick_fns_p<KT, 2>(r, one); break;
-    default: pick_fns_p<KT, 4>(r, one); break;
+    case 1: pick_fns_p<KT, 1, MS>(r, one); break;
+    case 2: pick_fns_p<KT, 2, MS>(r, one); break;
+    default: pick_fns_p<KT, 4, MS>(r, one); break;
   }
 }
 
-static void select_kernels(int K, int P, const void** r, const void** one) {
+// Kernels of a plan: by K (power-of-two K use the point-symmetric specialisations,
+// which every slot is checked against), with the multi-speed draw when the
+// plan's control set has several speeds.
+static void select_kernels(int K, int S, int P, const void** r, const void** one) {
+  if (S > 1) {
+    switch (K) {
+      case 4: pick_fns<4, true>(P, r, one); break;
+      case 8: pick_fns<8, true>(P, r, one); break;
+      case 16: pick_fns<16, true>(P, r, one); break;
+      default: pick_fns<32, true>(P, r, one); break;
+    }
+    return;
+  }
   switch (K) {
-    case 4: pick_fns<4>(P, r, one); break;
-    case 8: pick_fns<8>(P, r, one); break;
-    case 16: pick_fns<16>(P, r, one); break;
-    case 32: pick_fns<32>(P, r, one); break;
-    default: pick_fns<0>(P, r, one); break;
+    case 4: pick_fns<4, false>(P, r, one); break;
+    case 8: pick_fns<8, false>(P, r, one); break;
+    case 16: pick_fns<16, false>(P, r, one); break;
+    case 32: pick_fns<32, false>(P, r, one); break;
+    default: pick_fns<0, false>(P, r, one); break;
   }
 }
 
@@ -472,8 +487,11 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
   if (!cfg_in || !out) return fail(CAP_E_INVALID, "config or out is NULL");
   *out = nullptr;
   cap_plan_config cfg = *cfg_in;
-  cap_status st = check_model_shape(cfg.K, cfg.speed, cfg.dt);
+  Controls pc;
+  cap_status st = make_controls(cfg.K, cfg.speed, cfg.dt, cfg.n_speeds, cfg.speeds, 0u, &pc);
   if (st != CAP_OK) return st;
+  if (pc.S > 1 && cfg.K != 4 && cfg.K != 8 && cfg.K != 16 && cfg.K != 32)
+    return fail(CAP_E_UNSUPPORTED, "several speeds need K in {4, 8, 16, 32}");
   if (cfg.n_slots < 1 || cfg.n_slots > CAP_MAX_SLOTS) return fail(CAP_E_INVALID, "n_slots out of range");
   if (cfg.max_obs < 1 || cfg.max_obs > kMaxObs) return fail(CAP_E_INVALID, "max_obs must be in [1, 8]");
   if (cfg.ring == 0) cfg.ring = 2;
@@ -496,7 +514,7 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
   p->ring.resize(cfg.ring);
   p->per_tile = cfg.block_threads * cfg.particles_per_thread;
   p->cap_words = cfg.lds_bytes / (2 * (int)sizeof(uint32_t));
-  select_kernels(cfg.K, cfg.particles_per_thread, p->rollout_fn, p->rollout_one_fn);
+  select_kernels(cfg.K, pc.S, cfg.particles_per_thread, p->rollout_fn, p->rollout_one_fn);
   const size_t dyn = window_lds_bytes(p->cap_words, p->per_tile);
   hipError_t e = hipSuccess;
   for (int v = 0; v < 2; ++v) {
@@ -579,8 +597,10 @@ extern "C" cap_status cap_plan_set_slot(cap_plan* p, int32_t slot, const cap_slo
   if (slot < 0 || slot >= p->cfg.n_slots) return fail(CAP_E_INVALID, "slot out of range");
   HostSlot& hs = p->slots[slot];
   if (hs.active) return fail(CAP_E_CAPACITY, "slot is occupied");
-  cap_model m{p->cfg.K, p->cfg.speed, p->cfg.dt, d->B, d->beta, d->G, d->goals};
-  cap_status st = check_model(&m);
+  cap_model m{p->cfg.K, p->cfg.speed, p->cfg.dt, d->B, d->beta, d->G, d->goals,
+              p->cfg.n_speeds, p->cfg.speeds, d->speed_mask};
+  Controls c;
+  cap_status st = check_model(&m, &c);
   if (st != CAP_OK) return st;
   if ((st = check_grid(&d->grid)) != CAP_OK) return st;
   if (!d->counts_dev || !d->log_belief_dev || !d->belief_dev)
@@ -592,8 +612,7 @@ extern "C" cap_status cap_plan_set_slot(cap_plan* p, int32_t slot, const cap_slo
     return fail(CAP_E_INVALID, "smoothing needs probs_dev");
   HostSlot ns;
   std::memset(&ns.tmpl, 0, sizeof(SlotDev));
-  st = make_rollout_desc(m.K, m.speed, m.dt, m.B, m.beta, m.G, m.goals, d->grid, d->N, d->H,
-                         &ns.tmpl.rd);
+  st = make_rollout_desc(c, m.dt, m.B, m.beta, m.G, m.goals, d->grid, d->N, d->H, &ns.tmpl.rd);
   if (st != CAP_OK) return st;
   ns.grid = d->grid;
   if ((m.K == 4 || m.K == 8 || m.K == 16 || m.K == 32) && !ns.tmpl.rd.sym)
@@ -602,7 +621,7 @@ extern "C" cap_status cap_plan_set_slot(cap_plan* p, int32_t slot, const cap_slo
                            std::max(ns.tmpl.rd.Rx, ns.tmpl.rd.Ry))) != CAP_OK)
     return st;
   ns.tmpl.rd.human = d->human_id;
-  ns.tmpl.bm = make_belief_model(m.K, m.speed, m.dt, m.B, m.beta, m.G, m.goals);
+  ns.tmpl.bm = make_belief_model(c, m.dt, m.B, m.beta, m.G, m.goals);
   ns.tmpl.log_belief = d->log_belief_dev;
   ns.tmpl.smooth_r = d->smooth_radius;
   smooth_weights(d->smooth_sigma, d->smooth_radius, &ns.tmpl.smooth_w);
@@ -624,6 +643,21 @@ extern "C" cap_status cap_plan_clear_slot(cap_plan* p, int32_t slot) {
   if (slot < 0 || slot >= p->cfg.n_slots) return fail(CAP_E_INVALID, "slot out of range");
   p->slots[slot].active = false;
   p->slots[slot].n_staged = 0;
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_set_speed_mask(cap_plan* p, int32_t slot, uint32_t mask) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  if (slot < 0 || slot >= p->cfg.n_slots || !p->slots[slot].active)
+    return fail(CAP_E_INVALID, "slot is not active");
+  return set_speed_mask(&p->slots[slot].tmpl.rd, mask);
+}
+
+extern "C" cap_status cap_plan_reset_belief(cap_plan* p, int32_t slot) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  if (slot < 0 || slot >= p->cfg.n_slots || !p->slots[slot].active)
+    return fail(CAP_E_INVALID, "slot is not active");
+  p->slots[slot].reset = true;
   return CAP_OK;
 }
 

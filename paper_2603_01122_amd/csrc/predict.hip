@@ -37,26 +37,33 @@ __global__ void __launch_bounds__(256) normalize_kernel(const uint32_t* __restri
   for (size_t v = head * 4 + i; v < n; v += stride) p[v] = (float)c[v] / N;
 }
 
-template <int KT, int P, bool SHIFT>
+template <int KT, int P, bool SHIFT, bool MS>
 __global__ void __launch_bounds__(kPlainThreads)
     rollout_plain_kernel(const RolloutDesc d, uint32_t seed_lo, uint32_t seed_hi, int cap) {
   __shared__ TileShared sh;
+  __shared__ float4 ctl[MS ? CAP_MAX_U : 1];
   extern __shared__ uint32_t win[];
   for (int i = threadIdx.x; i < 2 * cap; i += blockDim.x) win[i] = 0u;
   // the first barrier inside rollout_tile orders this clear before any binning
   const int64_t first = (int64_t)blockIdx.x * P * blockDim.x;
-  rollout_tile<KT, P, SHIFT>(d, first, seed_lo, seed_hi, sh, win, cap);
+  rollout_tile<KT, P, SHIFT, MS>(d, first, seed_lo, seed_hi, sh, win, cap, ctl);
 }
 
-// Track simulator: one thread per track, the same heading draw as the rollout
+// Track simulator: one thread per track, the same control draw as the rollout
 // with the track's own (beta, goal) and the simulation counter domain.
-template <int KT>
+template <int KT, bool MS>
 __global__ void __launch_bounds__(256)
     simulate_kernel(const RolloutDesc d, int32_t n, int32_t T, const double* __restrict__ start,
                     const float* __restrict__ beta, const float* __restrict__ goal, double x0,
                     double y0, double cell, uint32_t stream_id, uint32_t seed_lo,
                     uint32_t seed_hi, int32_t* __restrict__ lat, float* __restrict__ pos) {
 #pragma clang fp contract(off)
+  __shared__ float4 ctl[MS ? CAP_MAX_U : 1];
+  if constexpr (MS) {
+    for (int u = threadIdx.x; u < d.K * d.S; u += blockDim.x)
+      ctl[u] = make_float4(d.T.fx[u], d.T.fy[u], d.T.s2[u], 0.f);
+    __syncthreads();
+  }
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const double q = cell / kLatticeScale;
@@ -73,11 +80,17 @@ __global__ void __launch_bounds__(256)
       if (s == 0) w = philox10((uint32_t)r, (uint32_t)((t - 1) >> 2), stream_id, 0xFFFFFFFFu,
                                seed_lo, seed_hi);
       const float u = uniform24f(pick_word(w, s));
-      const int k =
-          shift ? draw_heading<KT, true>((float)(X - GX), (float)(Y - GY), ib, u, d.T, d.K)
-                : draw_heading<KT, false>((float)(X - GX), (float)(Y - GY), ib, u, d.T, d.K);
-      X += d.Sx[k];
-      Y += d.Sy[k];
+      int k;
+      if constexpr (MS)
+        k = shift ? draw_control<KT, true>((float)(X - GX), (float)(Y - GY), ib, u, d.T, d.S,
+                                           d.smask, d.s_last, ctl)
+                  : draw_control<KT, false>((float)(X - GX), (float)(Y - GY), ib, u, d.T, d.S,
+                                            d.smask, d.s_last, ctl);
+      else
+        k = shift ? draw_heading<KT, true>((float)(X - GX), (float)(Y - GY), ib, u, d.T, d.K)
+                  : draw_heading<KT, false>((float)(X - GX), (float)(Y - GY), ib, u, d.T, d.K);
+      X += (int32_t)d.T.fx[k];
+      Y += (int32_t)d.T.fy[k];
     }
     const size_t o = ((size_t)r * (T + 1) + t) * 2;
     if (lat) {
@@ -106,17 +119,17 @@ cap_status launch_zero(uint32_t* p, size_t n, hipStream_t s) {
   return CAP_OK;
 }
 
-template <int KT, int P>
+template <int KT, int P, bool MS>
 static cap_status launch_plain_t(const RolloutDesc& d, uint32_t slo, uint32_t shi, int cap,
                                  hipStream_t s) {
   const int64_t per_block = (int64_t)P * kPlainThreads;
   const int64_t blocks = (d.N + per_block - 1) / per_block;
   const size_t lds = window_lds_bytes(cap, P * kPlainThreads);
   if (d.shift)
-    hipLaunchKernelGGL((rollout_plain_kernel<KT, P, true>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((rollout_plain_kernel<KT, P, true, MS>), dim3((unsigned)blocks),
                        dim3(kPlainThreads), lds, s, d, slo, shi, cap);
   else
-    hipLaunchKernelGGL((rollout_plain_kernel<KT, P, false>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((rollout_plain_kernel<KT, P, false, MS>), dim3((unsigned)blocks),
                        dim3(kPlainThreads), lds, s, d, slo, shi, cap);
   CAP_HIP(hipGetLastError());
   return CAP_OK;
@@ -124,13 +137,22 @@ static cap_status launch_plain_t(const RolloutDesc& d, uint32_t slo, uint32_t sh
 
 static cap_status launch_plain(const RolloutDesc& d, uint32_t slo, uint32_t shi, hipStream_t s) {
   const int cap = kPlainLdsBytes / (2 * (int)sizeof(uint32_t));
-  // specialised kernels assume a point-symmetric step table
+  // specialised kernels assume a point-symmetric step table; several speeds
+  // need one (checked when the descriptor is built)
+  if (d.S > 1) {
+    switch (d.K) {
+      case 4: return launch_plain_t<4, 1, true>(d, slo, shi, cap, s);
+      case 8: return launch_plain_t<8, 1, true>(d, slo, shi, cap, s);
+      case 16: return launch_plain_t<16, 1, true>(d, slo, shi, cap, s);
+      default: return launch_plain_t<32, 1, true>(d, slo, shi, cap, s);
+    }
+  }
   switch (d.sym ? d.K : 0) {
-    case 4: return launch_plain_t<4, 1>(d, slo, shi, cap, s);
-    case 8: return launch_plain_t<8, 1>(d, slo, shi, cap, s);
-    case 16: return launch_plain_t<16, 1>(d, slo, shi, cap, s);
-    case 32: return launch_plain_t<32, 1>(d, slo, shi, cap, s);
-    default: return launch_plain_t<0, 1>(d, slo, shi, cap, s);
+    case 4: return launch_plain_t<4, 1, false>(d, slo, shi, cap, s);
+    case 8: return launch_plain_t<8, 1, false>(d, slo, shi, cap, s);
+    case 16: return launch_plain_t<16, 1, false>(d, slo, shi, cap, s);
+    case 32: return launch_plain_t<32, 1, false>(d, slo, shi, cap, s);
+    default: return launch_plain_t<0, 1, false>(d, slo, shi, cap, s);
   }
 }
 
@@ -145,14 +167,15 @@ extern "C" cap_status cap_predict_occupancy(const cap_model* model, const cap_gr
                                             uint32_t* counts_dev, uint32_t* offgrid_dev,
                                             uint8_t* trace_k_dev, int32_t* trace_pair_dev,
                                             void* stream) {
-  cap_status st = check_model(model);
+  Controls c;
+  cap_status st = check_model(model, &c);
   if (st != CAP_OK) return st;
   if ((st = check_grid(grid)) != CAP_OK) return st;
   if (!z0 || !belief_dev || !counts_dev) return fail(CAP_E_INVALID, "z0, belief or counts is NULL");
   if (cycle >= 0x7FFFFFFFu) return fail(CAP_E_INVALID, "cycle must be < 2^31 - 1");
   RolloutDesc d;
-  st = make_rollout_desc(model->K, model->speed, model->dt, model->B, model->beta, model->G,
-                         model->goals, *grid, N, H, &d);
+  st = make_rollout_desc(c, model->dt, model->B, model->beta, model->G, model->goals, *grid, N,
+                         H, &d);
   if (st != CAP_OK) return st;
   if ((st = set_start(&d, z0[0], z0[1], *grid)) != CAP_OK) return st;
   d.human = human_id;
@@ -181,13 +204,15 @@ extern "C" cap_status cap_normalize(const uint32_t* counts_dev, int64_t n_cells,
   return CAP_OK;
 }
 
-extern "C" cap_status cap_simulate_tracks(int32_t K, double speed, double dt, double x0,
+extern "C" cap_status cap_simulate_tracks(int32_t K, double speed, int32_t n_speeds,
+                                          const double* speeds, double dt, double x0,
                                           double y0, double cell, int32_t n, int32_t T,
                                           const double* start_dev, const float* beta_dev,
                                           const float* goal_dev, uint64_t seed,
                                           uint32_t stream_id, int32_t* lat_dev, float* pos_dev,
                                           void* stream) {
-  cap_status st = check_model_shape(K, speed, dt);
+  Controls c;
+  cap_status st = make_controls(K, speed, dt, n_speeds, speeds, 0u, &c);
   if (st != CAP_OK) return st;
   if (n < 0 || T < 0 || T > (1 << 24)) return fail(CAP_E_INVALID, "n >= 0 and 0 <= T <= 2^24 required");
   if (!(cell > 0.0) || !std::isfinite(x0) || !std::isfinite(y0))
@@ -198,21 +223,25 @@ extern "C" cap_status cap_simulate_tracks(int32_t K, double speed, double dt, do
   const float zero2[2] = {0.f, 0.f};
   cap_grid g{x0, y0, cell, 1, 1};
   RolloutDesc d;
-  st = make_rollout_desc(K, speed, dt, 1, &one, 1, zero2, g, 1, 1, &d);
+  st = make_rollout_desc(c, dt, 1, &one, 1, zero2, g, 1, 1, &d);
   if (st != CAP_OK) return st;
   d.shift = 0;
   const uint32_t slo = (uint32_t)seed, shi = (uint32_t)(seed >> 32);
   const dim3 grid_dim((unsigned)((n + 255) / 256)), blk(256);
   hipStream_t s = as_stream(stream);
-#define CAP_SIM(KT)                                                                          \
-  hipLaunchKernelGGL((simulate_kernel<KT>), grid_dim, blk, 0, s, d, n, T, start_dev, beta_dev, \
+#define CAP_SIM(KT, MS)                                                                          \
+  hipLaunchKernelGGL((simulate_kernel<KT, MS>), grid_dim, blk, 0, s, d, n, T, start_dev, beta_dev, \
                      goal_dev, x0, y0, cell, stream_id, slo, shi, lat_dev, pos_dev)
-  switch (d.sym ? K : 0) {
-    case 4: CAP_SIM(4); break;
-    case 8: CAP_SIM(8); break;
-    case 16: CAP_SIM(16); break;
-    case 32: CAP_SIM(32); break;
-    default: CAP_SIM(0); break;
+  switch (d.S > 1 ? -K : (d.sym ? K : 0)) {
+    case -4: CAP_SIM(4, true); break;
+    case -8: CAP_SIM(8, true); break;
+    case -16: CAP_SIM(16, true); break;
+    case -32: CAP_SIM(32, true); break;
+    case 4: CAP_SIM(4, false); break;
+    case 8: CAP_SIM(8, false); break;
+    case 16: CAP_SIM(16, false); break;
+    case 32: CAP_SIM(32, false); break;
+    default: CAP_SIM(0, false); break;
   }
 #undef CAP_SIM
   CAP_HIP(hipGetLastError());

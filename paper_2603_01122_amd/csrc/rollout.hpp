@@ -12,13 +12,15 @@ namespace capred {
 // value to the single-human kernel and stored in device memory for batches).
 struct RolloutDesc {
   int32_t N, H, K, B, G, nx, ny;
+  int32_t S;                // speeds (controls u = s K + k, U = S K)
+  int32_t s_last;           // last allowed speed
+  uint32_t smask;           // allowed speeds of the prediction (bit s)
   int32_t X0, Y0;           // start on the lattice (grid frame)
   int32_t Rx, Ry;           // max |S_kx|, |S_ky|: reach per step, lattice units
   uint32_t human, cycle;
   int32_t shift;            // 1: subtract the largest exponent (large beta * step)
   int32_t sym;              // 1: S_{k+K/2} = -S_k for every k < K/2 (K even)
-  HeadingTable T;           // lattice-unit steps and squared lengths (FP32)
-  int32_t Sx[CAP_MAX_K], Sy[CAP_MAX_K];
+  HeadingTable T;           // lattice-unit steps (exact integers) and squared lengths (FP32)
   float ibeta[CAP_MAX_B];   // 1 / (-beta q log2(e)), q = lattice pitch
   int32_t GX[CAP_MAX_G], GY[CAP_MAX_G];
   const double* belief;     // [G][B]
@@ -30,7 +32,7 @@ struct RolloutDesc {
 
 struct TileShared {
   double P[CAP_MAX_J];      // pair CDF (sequential FP64 prefix sums)
-  int2 S[CAP_MAX_K];        // lattice steps for the dynamic heading index
+  int2 S[CAP_MAX_K];        // lattice steps for the dynamic heading index (one speed)
   int2 goal[CAP_MAX_G];
   float ibeta[CAP_MAX_B];
   uint32_t off[2];          // off-grid counters of the two in-flight steps
@@ -79,9 +81,14 @@ __host__ __device__ constexpr size_t window_lds_bytes(int cap, int particles_per
 // on exit (cap <= 65536).  A step's window is flushed from the list of words
 // its particles touched first, so the flush costs one entry per occupied
 // word, whatever the window's area.
-template <int KT, int P, bool SHIFT>
+//
+// MS (several speeds): draw_control over the S K controls; `ctl` is an LDS
+// array of CAP_MAX_U float4 that receives (fx, fy, s2) of every control, read
+// per lane for the block recomputation and the step (unused otherwise).
+template <int KT, int P, bool SHIFT, bool MS>
 __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_lo,
-                             uint32_t seed_hi, TileShared& sh, uint32_t* win, int cap) {
+                             uint32_t seed_hi, TileShared& sh, uint32_t* win, int cap,
+                             float4* ctl) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int J = d.G * d.B;
@@ -100,7 +107,12 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     sh.off[1] = 0u;
     sh.ntouch[0] = sh.ntouch[1] = sh.ntouch[2] = 0u;
   }
-  for (int k = tid; k < d.K; k += nthr) sh.S[k] = make_int2(d.Sx[k], d.Sy[k]);
+  if constexpr (MS) {
+    for (int u = tid; u < d.K * d.S; u += nthr)
+      ctl[u] = make_float4(d.T.fx[u], d.T.fy[u], d.T.s2[u], 0.f);
+  } else {
+    for (int k = tid; k < d.K; k += nthr) sh.S[k] = make_int2((int)d.T.fx[k], (int)d.T.fy[k]);
+  }
   for (int g = tid; g < d.G; g += nthr) sh.goal[g] = make_int2(d.GX[g], d.GY[g]);
   for (int b = tid; b < d.B; b += nthr) sh.ibeta[b] = d.ibeta[b];
   __syncthreads();
@@ -167,11 +179,22 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
       // computed for inactive lanes too (harmless state), so that the P
       // particles stay in one basic block; only emplacement is predicated
       const float u = uniform24f(pick_word(rw[p], s));
-      const int k = draw_heading<KT, SHIFT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p],
-                                            u, d.T, d.K);
-      const int2 st = sh.S[k];
-      X[p] += st.x;
-      Y[p] += st.y;
+      int k;
+      if constexpr (MS)
+        k = draw_control<KT, SHIFT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p], u, d.T,
+                                    d.S, d.smask, d.s_last, ctl);
+      else
+        k = draw_heading<KT, SHIFT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p], u,
+                                    d.T, d.K);
+      if constexpr (MS) {
+        const float4 c = ctl[k];
+        X[p] += (int32_t)c.x;
+        Y[p] += (int32_t)c.y;
+      } else {
+        const int2 st = sh.S[k];
+        X[p] += st.x;
+        Y[p] += st.y;
+      }
       bool fresh = false;     // this lane turned an empty window word non-empty
       uint32_t widx = 0;
       if (act[p]) {

@@ -61,10 +61,23 @@ class Server:
     def __init__(self, K: int, speed: float, dt: float, n_slots: int, max_H: int, max_nx: int,
                  max_ny: int, max_G: int, max_B: int, ring: int = 2, n_streams: int = 2,
                  particle_budget: Optional[int] = None, seed: int = 0, probs: bool = True,
-                 tuning: Optional[dict] = None, max_smooth_radius: int = 0, device="cuda"):
+                 tuning: Optional[dict] = None, max_smooth_radius: int = 0, speeds=None,
+                 stationary: Optional[Tuple[float, int]] = None,
+                 goal_departure: Optional[float] = None, device="cuda"):
+        """stationary = (eps, mask): a human whose newest observed step is shorter
+        than eps metres is predicted with the allowed speeds `mask` only (Q = -inf
+        for the others, Sec. IV-B) until it moves again.  goal_departure = r: a
+        human that was within r metres of one of its goals and is now farther
+        from all of them gets a uniform belief before the next update (Sec. IV-B).
+        The paper specifies neither detector; these are the simplest readings."""
         tuning = tuning or {}
         self.plan = capred.Plan(K, speed, dt, n_slots, max_obs=1, ring=ring,
-                                max_smooth_radius=max_smooth_radius, **tuning)
+                                max_smooth_radius=max_smooth_radius, speeds=speeds, **tuning)
+        self.stationary = stationary
+        self.goal_departure = goal_departure
+        self._last_xy: Dict[int, np.ndarray] = {}
+        self._at_goal: Dict[int, bool] = {}
+        self._masked: Dict[int, bool] = {}
         self.K, self.ring, self.seed = K, ring, seed
         self.max = (max_H, max_nx, max_ny, max_G, max_B)
         cells = max_H * max_nx * max_ny
@@ -82,6 +95,11 @@ class Server:
         self.budget = particle_budget
         self.in_use = 0
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        # The pools are filled on the caller's current stream; the serving streams
+        # must not start before those fills (nor before any later host-driven
+        # write to a slot's buffers, see _after_current_stream).
+        self._dep: Optional[torch.cuda.Event] = None
+        self._after_current_stream()
         self.cycle = 0
         self.records: List[CycleRecord] = []
         self._pending: collections.deque = collections.deque()
@@ -95,6 +113,8 @@ class Server:
         self.waiting.append(r)
 
     def depart(self, hid: int):
+        for d in (self._last_xy, self._at_goal, self._masked):
+            d.pop(hid, None)
         if hid in self.slot_of:
             s = self.slot_of.pop(hid)
             self.plan.retire(s)
@@ -124,6 +144,7 @@ class Server:
                 buf = self._views(s, r)
                 if r.log_belief is not None:
                     buf.log_belief.copy_(torch.as_tensor(r.log_belief, dtype=torch.float64))
+                    self._after_current_stream()
                 self.plan.admit(s, r.hid, r.model, r.grid, r.N, r.H, r.last_xy, buf,
                                 reset_belief=r.log_belief is None, smooth=r.smooth)
                 self.slot_of[r.hid] = s
@@ -141,8 +162,13 @@ class Server:
         self._admit_waiting()
         for hid, xy in observations.items():
             if hid in self.slot_of:
+                self._detect(hid, xy)
                 self.plan.stage(self.slot_of[hid], xy)
         stream = self.streams[self.cycle % len(self.streams)]
+        if self._dep is not None:
+            for st in self.streams:
+                st.wait_event(self._dep)
+            self._dep = None
         ev = torch.cuda.Event()
         with torch.cuda.stream(stream):
             if plain:
@@ -157,6 +183,32 @@ class Server:
         self._pending.append(rec)
         self.cycle += 1
         return rec
+
+    def _after_current_stream(self):
+        """Orders the next cycle after the work queued so far on the current stream."""
+        self._dep = torch.cuda.Event()
+        self._dep.record(torch.cuda.current_stream())
+
+    def _detect(self, hid: int, xy):
+        """Stationary and goal-departure detection on the newest observation."""
+        s = self.slot_of[hid]
+        z = np.asarray(xy, np.float64)
+        prev = self._last_xy.get(hid)
+        if prev is None:
+            prev = np.asarray(self.req[hid].last_xy, np.float64)
+        if self.stationary is not None:
+            eps, slow = self.stationary
+            still = bool(np.hypot(*(z - prev)) < eps)
+            if still != self._masked.get(hid, False):
+                self.plan.set_speed_mask(s, slow if still else self.req[hid].model.speed_mask)
+                self._masked[hid] = still
+        if self.goal_departure is not None:
+            d = np.min(np.hypot(*(self.req[hid].model.goals.astype(np.float64) - z).T))
+            near = bool(d <= self.goal_departure)
+            if self._at_goal.get(hid, False) and not near:
+                self.plan.reset_belief(s)
+            self._at_goal[hid] = near
+        self._last_xy[hid] = z
 
     def poll(self) -> int:
         """Marks finished cycles (non-blocking); returns how many are still pending."""

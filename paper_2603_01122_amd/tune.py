@@ -28,14 +28,23 @@ CACHE = os.environ.get("CAPRED_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "capred_tune.json"))
 
 
-def signature(humans, plain: bool) -> str:
-    key = json.dumps({
-        "device": torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none",
-        "cus": capred.device_cu_count(),
-        "plain": plain,
-        "humans": [(h.K, h.N, h.H, h.G, h.B, tuple(h.grid)) for h in humans],
+def signature_key(humans, plain: bool) -> str:
+    """Device architecture and CU count plus the workload's shape."""
+    arch = "none"
+    if torch.cuda.is_available():
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    return json.dumps({
+        "arch": arch,
+        "cus": int(capred.device_cu_count()),
+        "plain": bool(plain),
+        "humans": [[int(h.K), int(h.N), int(h.H), int(h.G), int(h.B),
+                    [float(h.grid[0]), float(h.grid[1]), float(h.grid[2]), int(h.grid[3]),
+                     int(h.grid[4])]] for h in humans],
     }, sort_keys=True)
-    return hashlib.sha1(key.encode()).hexdigest()
+
+
+def signature(humans, plain: bool) -> str:
+    return hashlib.sha1(signature_key(humans, plain).encode()).hexdigest()
 
 
 def time_candidate(humans, tracks: Dict[int, np.ndarray], cand: Dict[str, int], cycles: int = 6,
@@ -151,7 +160,7 @@ def main():
         best = json.loads(min(times, key=times.get))
         table[signature(humans, plain)] = {
             "best": best, "scene": args.scene, "plain": plain,
-            "device": torch.cuda.get_device_name(0),
+            "device": torch.cuda.get_device_name(0), "key": signature_key(humans, plain),
             "ms_per_cycle": {k: round(v * 1e3, 4) for k, v in sorted(times.items())}}
         print(f"{'plain' if plain else 'batched'}: best {best}", flush=True)
         for k, v in sorted(times.items(), key=lambda kv: kv[1]):

@@ -110,5 +110,30 @@ def test_invalid_loglik_and_workspace(cap):
     assert rc == cap.CAP_E_INVALID
     rc = cap._lib.cap_philox_blocks(-1, 0, 0, 0, 0, 0, p, None)
     assert rc == cap.CAP_E_INVALID
-    rc = cap._lib.cap_simulate_tracks(8, 1.0, 0.1, 0, 0, 0.0, 4, 10, p, p, p, 0, 0, p, p, None)
+    rc = cap._lib.cap_simulate_tracks(8, 1.0, 0, None, 0.1, 0, 0, 0.0, 4, 10, p, p, p, 0, 0, p, p,
+                                      None)
     assert rc == cap.CAP_E_INVALID
+
+
+def test_invalid_control_sets(cap):
+    """Multi-speed control sets are validated on the host before any launch."""
+    p = C.c_void_p(256)
+    grid = cap.grid_c((0.0, 0.0, 0.1, 16, 16))
+    z0 = (C.c_double * 2)(0.8, 0.8)
+
+    def predict(m):
+        return cap._lib.cap_predict_occupancy(C.byref(m.c()), C.byref(grid), z0, p, 100, 5, 0, 0,
+                                              0, p, p, None, None, None)
+    beta, goals = np.ones(2, np.float32), np.array([[1.0, 1.0]], np.float32)
+    cases = [
+        (cap.Model(16, 1.0, 0.1, beta, goals, speeds=np.full(9, 0.5)), cap.CAP_E_INVALID),
+        (cap.Model(16, 1.0, 0.1, beta, goals, speeds=[0.5, 0.0]), cap.CAP_E_INVALID),
+        (cap.Model(32, 1.0, 0.1, beta, goals, speeds=[0.3, 0.6, 0.9, 1.2, 1.5]), cap.CAP_E_INVALID),
+        (cap.Model(16, 1.0, 0.1, beta, goals, speeds=[0.5, 1.0], speed_mask=0b100),
+         cap.CAP_E_INVALID),
+        (cap.Model(12, 1.0, 0.1, beta, goals, speeds=[0.5, 1.0]), cap.CAP_E_UNSUPPORTED),
+    ]
+    for m, want in cases:
+        assert predict(m) == want, cap._lib.cap_last_error().decode()
+    assert cap._lib.cap_simulate_tracks(16, 1.0, 2, (C.c_double * 2)(0.5, -1.0), 0.1, 0, 0, 0.1,
+                                        4, 10, p, p, p, 0, 0, p, p, None) == cap.CAP_E_INVALID
