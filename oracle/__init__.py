@@ -116,6 +116,10 @@ def lib():
             L.orc_smooth.restype = i32
             L.orc_union_max.argtypes = [C.POINTER(C.POINTER(C.c_float)), i32, i64, _f32p]
             L.orc_union_max.restype = i32
+            L.orc_mppi.argtypes = [_f64p, _f64p, i32, d, i32, _f64p, _f64p, _nullable(_f32p), i32,
+                                   d, d, d, i32, i32, _f64p, _f64p, _f64p, d, d, d, d, _f64p,
+                                   _f64p, _nullable(_i32p)]
+            L.orc_mppi.restype = i32
             _lib = L
     return _lib
 
@@ -342,3 +346,35 @@ def union_max(grids) -> np.ndarray:
     out = np.empty(shape, np.float32)
     _check(lib().orc_union_max(ptrs, len(arrs), arrs[0].size, out.reshape(-1)), "union_max")
     return out
+
+
+# ------------------------------------------------------------------------ MPPI
+PAPER_MPPI_COST = dict(Q=(3.0, 3.0, 10.0, 0.0), Qf=(0.6, 0.6, 2.0, 0.0), R=(2.0, 1.0),
+                       w_coll=1000.0, p_coll=0.1)
+
+
+def mppi(*, z0, goal, U, delta, dt, tau, Q, Qf, R, w_coll=1000.0, p_coll=0.1, c_time=0.0,
+         occ=None, grid=None):
+    """One MPPI step (Sec. III-C) in FP64.  U [T,2] (a, omega); delta [T,N,2].
+    Returns (S [N], U_new [T,2], near [N]: steps within 1e-9 m of a cell edge)."""
+    U = np.ascontiguousarray(U, np.float64).reshape(-1, 2)
+    T = U.shape[0]
+    delta = np.ascontiguousarray(delta, np.float64)
+    assert delta.shape[0] == T and delta.shape[2] == 2
+    N = delta.shape[1]
+    if occ is not None:
+        occ = np.ascontiguousarray(occ, np.float32)
+        H = occ.shape[0]
+        x0, y0, cell, nx, ny = grid
+    else:
+        H, x0, y0, cell, nx, ny = 0, 0.0, 0.0, 1.0, 1, 1
+    S = np.empty(N, np.float64)
+    Un = np.empty((T, 2), np.float64)
+    near = np.empty(N, np.int32)
+    f = lambda v, n: np.ascontiguousarray(v, np.float64).reshape(n)
+    _check(lib().orc_mppi(f(z0, 4), f(goal, 4), T, dt, N, U.reshape(-1), delta.reshape(-1),
+                          None if occ is None else occ.reshape(-1), H, float(x0), float(y0),
+                          float(cell), int(nx), int(ny), f(Q, 4), f(Qf, 4), f(R, 2),
+                          float(w_coll), float(p_coll), float(c_time), float(tau), S,
+                          Un.reshape(-1), near), "mppi")
+    return S, Un, near

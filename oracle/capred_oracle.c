@@ -699,3 +699,83 @@ int orc_union_max(const float* const* grids, int n_humans, int64_t n, float* out
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* MPPI consumer of the predictions (Sec. III-C, local planner), FP64.
+ * Robot: 4-D Dubins car z = (x, y, v, theta) with controls u = (a, omega)
+ * (Eq. robot_model), forward Euler over dt:
+ *   x += v cos(theta) dt,  y += v sin(theta) dt,  v += a dt,  theta += omega dt.
+ * Sample i applies u'_t = U_t + delta_{t,i} for t = 1..T (delta laid out
+ * [T][N][2]) from z_0 and accumulates
+ *   S_i = sum_{t<T} [ (z_t-g)' Q (z_t-g) + u'_t' diag(R) u'_t
+ *                     + w_coll * 1{p_t(z_t) >= p_coll} + c_time ]
+ *       + (z_T-g)' Qf (z_T-g),
+ * with p_t the occupancy probability of the cell holding (x_t, y_t) in grid
+ * t of occ [H][ny][nx] (0 off the grid, or when t > H).  Then
+ *   U*_t = U_t + sum_i w_i delta_{t,i} / sum_i w_i,  w_i = exp(-(S_i - min S)/tau)
+ * (the weighted average of the paper's update, shifted by min S, which
+ * cancels).  near[i] (nullable) counts the steps of sample i that read the
+ * grid at a position within 1e-9 m of a cell edge, where another
+ * implementation's rounding may pick the neighbouring cell.  Readings: the
+ * control cost is the quadratic u' diag(R) u (the cost is called quadratic;
+ * the printed R^T u is read as that), the collision probability of the robot at
+ * step t is the predicted occupancy of its cell in grid t, and the robot step
+ * equals the prediction step. */
+int orc_mppi(const double* z0, const double* goal, int T, double dt, int N, const double* U,
+             const double* delta, const float* occ, int H, double x0, double y0, double cell,
+             int nx, int ny, const double* Q, const double* Qf, const double* R, double w_coll,
+             double p_coll, double c_time, double tau, double* S, double* U_out,
+             int32_t* near) {
+  if (T < 1 || N < 1 || !(dt > 0) || !(tau > 0) || !(cell > 0) || nx < 1 || ny < 1 || H < 0)
+    return -1;
+  for (int i = 0; i < N; ++i) {
+    double x = z0[0], y = z0[1], v = z0[2], th = z0[3];
+    double s = 0.0;
+    int nn = 0;
+    for (int t = 1; t <= T; ++t) {
+      const double a = U[2 * (t - 1)] + delta[((int64_t)(t - 1) * N + i) * 2];
+      const double w = U[2 * (t - 1) + 1] + delta[((int64_t)(t - 1) * N + i) * 2 + 1];
+      const double nxp = x + v * cos(th) * dt, nyp = y + v * sin(th) * dt;
+      v = v + a * dt;
+      th = th + w * dt;
+      x = nxp;
+      y = nyp;
+      const double e[4] = {x - goal[0], y - goal[1], v - goal[2], th - goal[3]};
+      if (t < T) {
+        for (int k = 0; k < 4; ++k) s += Q[k] * e[k] * e[k];
+        s += R[0] * a * a + R[1] * w * w;
+        const double fx = (x - x0) / cell, fy = (y - y0) / cell;
+        const double cx = floor(fx), cy = floor(fy);
+        if (occ && t <= H &&
+            (fabs(fx - rint(fx)) * cell < 1e-9 || fabs(fy - rint(fy)) * cell < 1e-9))
+          ++nn;
+        if (occ && t <= H && cx >= 0 && cx < nx && cy >= 0 && cy < ny) {
+          const float p = occ[((int64_t)(t - 1) * ny + (int64_t)cy) * nx + (int64_t)cx];
+          if ((double)p >= p_coll) s += w_coll;
+        }
+        s += c_time;
+      } else {
+        for (int k = 0; k < 4; ++k) s += Qf[k] * e[k] * e[k];
+      }
+    }
+    S[i] = s;
+    if (near) near[i] = nn;
+  }
+  double smin = INFINITY;
+  for (int i = 0; i < N; ++i) if (S[i] < smin) smin = S[i];
+  double den = 0.0;
+  double* wts = (double*)malloc(sizeof(double) * N);
+  if (!wts) return -2;
+  for (int i = 0; i < N; ++i) {
+    wts[i] = exp(-(S[i] - smin) / tau);
+    den += wts[i];
+  }
+  for (int t = 0; t < T; ++t)
+    for (int k = 0; k < 2; ++k) {
+      double num = 0.0;
+      for (int i = 0; i < N; ++i) num += wts[i] * delta[((int64_t)t * N + i) * 2 + k];
+      U_out[2 * t + k] = U[2 * t + k] + num / den;
+    }
+  free(wts);
+  return 0;
+}
