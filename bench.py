@@ -167,6 +167,38 @@ def profiled_traffic(best):
     return int(fields["traffic_bytes_per_launch"])
 
 
+def mppi_timing(capred, torch, np, srv, humans, cycle, reps=20):
+    """Union of the 16 humans' newest grids (point-wise max) and one MPPI step
+    (N = 8192 samples, T = 40) of a robot crossing the scene, on the GPU right
+    after a serving cycle: the prediction consumer of Sec. III-C."""
+    probs = [srv.grids(h.hid, cycle)[1] for h in humans]
+    grid = humans[0].grid
+    T, N = 40, 8192
+    r = np.random.default_rng(11)
+    delta = torch.tensor(r.normal(scale=[0.8, 0.6], size=(T, N, 2)), device="cuda")
+    U = torch.zeros((T, 2), dtype=torch.float64, device="cuda")
+    S = torch.empty(N, dtype=torch.float64, device="cuda")
+    occ = torch.empty_like(probs[0])
+    z0, goal = (1.0, 1.0, 0.8, 0.7), (11.0, 11.0, 0.0, 0.0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tu, tm = [], []
+    for k in range(reps + 2):
+        ev[0].record()
+        capred.union_max(probs, out=occ)
+        ev[1].record()
+        capred.mppi_step(z0, goal, U, delta, dt=humans[0].dt, tau=10.0, occ=occ, grid=grid, S=S,
+                         **capred.PAPER_MPPI_COST)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if k >= 2:
+            tu.append(ev[0].elapsed_time(ev[1]))
+            tm.append(ev[1].elapsed_time(ev[2]))
+    cells = occ.numel()
+    return {"union_ms": round(float(np.median(tu)), 4),
+            "union_GBps": round(cells * 4 * (len(probs) + 1) / (np.median(tu) * 1e-3) / 1e9, 1),
+            "mppi_ms": round(float(np.median(tm)), 4), "samples": N, "horizon": T}
+
+
 def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
     """The 64-human x 2^20-particle, K = 32, H = 200 scene: batched cycles
     back to back and the rollout kernel's share of the ALU roofline."""
@@ -378,6 +410,10 @@ def main():
                         args.paced_cycles, args.rate,
                         progress=(2000, lambda k: log(f"  paced {k} cycles")))
         c += args.paced_cycles
+    srv.drain()
+    mppi = mppi_timing(capred, torch, np, srv, humans, c - 1)
+    log(f"union of 16 grids {mppi['union_ms']} ms ({mppi['union_GBps']} GB/s), "
+        f"MPPI step {mppi['mppi_ms']} ms")
     srv.close()
 
     # ---------------------------------------------------------- plain per-human launches
@@ -447,6 +483,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "largest_scene": largest,
+        "consumer": mppi,
         "tab1_shaped": tab1,
         "context": "paper: ~125 Hz for one human, n=8192, T=10, |U|=96 on an RTX 2080 Ti "
                    "(Tab. 1, JAX/XLA), about 1.0e7 particle-steps/s; different workload and hardware",

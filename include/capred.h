@@ -327,6 +327,38 @@ cap_status cap_plan_tuning(const cap_plan* plan, cap_plan_config* out);
 cap_status cap_plan_run_plain(cap_plan* plan, uint64_t seed, uint32_t cycle, void* stream);
 
 /* ------------------------------------------------------------------------
+ * MPPI consumer of the predictions (Sec. III-C, local planner; weights of the
+ * running example).  Robot: 4-D Dubins car z = (x, y, v, theta), controls
+ * u = (a, omega) (Eq. robot_model), forward Euler over dt.  Sample i applies
+ * u'_t = U_t + delta_{t,i}, t = 1..T, from z0 and costs
+ *   S_i = sum_{t<T} [ (z_t-g)' diag(Q) (z_t-g) + u'_t' diag(R) u'_t
+ *                     + w_coll [p_t(z_t) >= p_coll] + c_time ]
+ *         + (z_T-g)' diag(Qf) (z_T-g),
+ * p_t(z) = occupancy probability of the cell holding (x, y) in prediction grid
+ * t (occ [H][ny][nx], the robot step equal to the prediction step; 0 off the
+ * grid or for t > H).  Then U_t += sum_i w_i delta_{t,i} / sum_i w_i with
+ * w_i = exp(-(S_i - min S) / tau).  FP64 throughout (the collision term is a
+ * step function of the cell).
+ *   z0, goal: host [4]; U_dev [T][2] FP64 in/out; delta_dev [T][N][2] FP64,
+ *   16-byte aligned (perturbations drawn by the caller); occ_dev FP32 or NULL
+ *   (no collision term); S_dev [N] FP64 out.  1 <= T <= 65535, 1 <= N <= 2^24.
+ * Errors: CAP_E_INVALID for bad sizes, tau <= 0, NULL or misaligned buffers. */
+typedef struct cap_mppi_cost {
+  double Q[4];     /* running state weights (paper: 3, 3, 10, 0)    */
+  double Qf[4];    /* terminal state weights (paper: Q / 5)          */
+  double R[2];     /* control weights (paper: 2, 1)                  */
+  double w_coll;   /* collision penalty (paper: 1000)                */
+  double p_coll;   /* collision probability threshold (paper: 0.1)  */
+  double c_time;   /* per-step time cost (the planning interval)     */
+  double tau;      /* temperature, > 0                               */
+} cap_mppi_cost;
+
+cap_status cap_mppi_step(const double z0[4], const double goal[4], int32_t T, double dt,
+                         int32_t N, double* U_dev, const double* delta_dev, const float* occ_dev,
+                         int32_t H, const cap_grid* grid, const cap_mppi_cost* cost,
+                         double* S_dev, void* stream);
+
+/* ------------------------------------------------------------------------
  * Measurement probes for the roofline of the rollout (not part of the method):
  * cap_probe runs `blocks` x 256 threads, each issuing 8 independent chains of
  * `iters` operations of one kind: 0 FP32 FMA, 1 exp2, 2 sqrt, 3 reciprocal,

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcapred.so")
 SOURCES = ["abi.hip", "belief.hip", "predict.hip", "loglik.hip", "plan.hip", "probe.hip",
-           "smooth.hip"]
+           "smooth.hip", "mppi.hip"]
 ARCH = "gfx950"
 
 

@@ -46,6 +46,12 @@ class cap_model(C.Structure):
                 ("speeds", C.POINTER(C.c_double)), ("speed_mask", C.c_uint32)]
 
 
+class cap_mppi_cost(C.Structure):
+    _fields_ = [("Q", C.c_double * 4), ("Qf", C.c_double * 4), ("R", C.c_double * 2),
+                ("w_coll", C.c_double), ("p_coll", C.c_double), ("c_time", C.c_double),
+                ("tau", C.c_double)]
+
+
 class cap_grid(C.Structure):
     _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("cell", C.c_double), ("nx", C.c_int32),
                 ("ny", C.c_int32)]
@@ -92,6 +98,8 @@ _sig("cap_predict_occupancy", _i32, C.POINTER(cap_model), C.POINTER(cap_grid),
 _sig("cap_normalize", _i32, _vp, _i64, _i32, _vp, _vp)
 _sig("cap_smooth_occupancy", _i32, _vp, _i32, _i32, _i32, _i32, C.c_double, _i32, _vp, _vp)
 _sig("cap_union_max", _i32, C.POINTER(_vp), _i32, _i64, _vp, _vp)
+_sig("cap_mppi_step", _i32, C.POINTER(C.c_double), C.POINTER(C.c_double), _i32, _d, _i32, _vp, _vp,
+     _vp, _i32, _vp, C.POINTER(cap_mppi_cost), _vp, _vp)
 _sig("cap_simulate_tracks", _i32, _i32, _d, _i32, C.POINTER(C.c_double), _d, _d, _d, _d, _i32,
      _i32, _vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp)
 _sig("cap_loglik", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp)
@@ -104,7 +112,7 @@ _sig("cap_copy", _i32, _vp, _vp, _sz, _vp)
 EXPORTED = ["cap_probe", "cap_copy", "cap_philox_blocks", "cap_abi_version", "cap_last_error", "cap_device_cu_count", "cap_belief_update",
             "cap_belief_reset", "cap_predict_occupancy", "cap_normalize", "cap_simulate_tracks",
             "cap_loglik", "cap_loglik_backward", "cap_loglik_backward_workspace",
-            "cap_smooth_occupancy", "cap_union_max"]
+            "cap_smooth_occupancy", "cap_union_max", "cap_mppi_step"]
 if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_create", _i32, C.POINTER(cap_plan_config), C.POINTER(_vp))
     _sig("cap_plan_destroy", None, _vp)
@@ -300,6 +308,39 @@ def union_max(grids: Sequence[torch.Tensor], out: Optional[torch.Tensor] = None,
                               _ptr(out, torch.float32, "out", shape), _stream(stream)),
            "cap_union_max")
     return out
+
+
+PAPER_MPPI_COST = dict(Q=(3.0, 3.0, 10.0, 0.0), Qf=(0.6, 0.6, 2.0, 0.0), R=(2.0, 1.0),
+                       w_coll=1000.0, p_coll=0.1)
+
+
+def mppi_step(z0: Sequence[float], goal: Sequence[float], U: torch.Tensor, delta: torch.Tensor,
+              dt: float, tau: float, Q=(3.0, 3.0, 10.0, 0.0), Qf=(0.6, 0.6, 2.0, 0.0),
+              R=(2.0, 1.0), w_coll: float = 1000.0, p_coll: float = 0.1, c_time: float = 0.0,
+              occ: Optional[torch.Tensor] = None, grid: Optional[Sequence] = None,
+              S: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """One MPPI step (Sec. III-C) of the 4-D Dubins robot against the predicted
+    grids occ [H, ny, nx] (FP32, or None): updates U [T, 2] (FP64, in place)
+    from perturbations delta [T, N, 2] (FP64) and returns the costs S [N]."""
+    if U.dim() != 2 or U.shape[1] != 2 or delta.dim() != 3 or delta.shape[0] != U.shape[0] \
+            or delta.shape[2] != 2:
+        raise ValueError("U must be [T, 2] and delta [T, N, 2]")
+    T, N = U.shape[0], delta.shape[1]
+    if S is None:
+        S = torch.empty(N, dtype=torch.float64, device=U.device)
+    cost = cap_mppi_cost((C.c_double * 4)(*Q), (C.c_double * 4)(*Qf), (C.c_double * 2)(*R),
+                         float(w_coll), float(p_coll), float(c_time), float(tau))
+    H = 0 if occ is None else occ.shape[0]
+    g = None if occ is None else C.byref(grid_c(grid))
+    if occ is not None and tuple(occ.shape[1:]) != (int(grid[4]), int(grid[3])):
+        raise ValueError("occ must be [H, ny, nx] of the grid")
+    _check(_lib.cap_mppi_step((C.c_double * 4)(*[float(x) for x in z0]),
+                              (C.c_double * 4)(*[float(x) for x in goal]), T, float(dt), N,
+                              _ptr(U, torch.float64, "U"), _ptr(delta, torch.float64, "delta"),
+                              _ptr(occ, torch.float32, "occ"), H, g, C.byref(cost),
+                              _ptr(S, torch.float64, "S", (N,)), _stream(stream)),
+           "cap_mppi_step")
+    return S
 
 
 def philox_blocks(n: int, c0: int, c1: int, c2: int, c3: int, seed: int, device="cuda",

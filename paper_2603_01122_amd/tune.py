@@ -129,10 +129,12 @@ def main():
     ap.add_argument("--cycles", type=int, default=30, help="timed cycles per candidate")
     ap.add_argument("--repeats", type=int, default=3, help="timings per candidate (min taken)")
     ap.add_argument("--no-plain", action="store_true", help="tune the batched launch only")
+    ap.add_argument("--lds", type=str, default="",
+                    help="comma-separated LDS window budgets (bytes) to try besides the default")
     args = ap.parse_args()
     scene = getattr(scenes, args.scene)()
     humans = scene.humans
-    T = 16 + args.repeats * (args.cycles + 3) * len(CANDIDATES)
+    T = 16 + args.cycles + 3
     h0 = humans[0]
     _, pos = capred.simulate_tracks(
         h0.K, h0.speed, h0.dt, h0.frame,
@@ -147,10 +149,13 @@ def main():
         table = json.load(open(SHIPPED))
     except (OSError, ValueError):
         table = {}
+    cands = list(CANDIDATES)
+    for lds in (int(x) for x in args.lds.split(",") if x):
+        cands += [dict(c, lds_bytes=lds) for c in CANDIDATES]
     for plain in ((False,) if args.no_plain else (False, True)):
         times = {}
         for _ in range(args.repeats):
-            for cand in CANDIDATES:
+            for cand in (cands if not plain else CANDIDATES):
                 try:
                     t = time_candidate(humans, tracks, cand, cycles=args.cycles, plain=plain)
                 except capred.CapError:

@@ -137,3 +137,23 @@ def test_invalid_control_sets(cap):
         assert predict(m) == want, cap._lib.cap_last_error().decode()
     assert cap._lib.cap_simulate_tracks(16, 1.0, 2, (C.c_double * 2)(0.5, -1.0), 0.1, 0, 0, 0.1,
                                         4, 10, p, p, p, 0, 0, p, p, None) == cap.CAP_E_INVALID
+
+
+def test_invalid_mppi(cap):
+    """MPPI arguments are validated on the host before any launch."""
+    p = C.c_void_p(256)
+    z = (C.c_double * 4)(0, 0, 1, 0)
+    grid = cap.grid_c((0.0, 0.0, 0.1, 16, 16))
+
+    def cost(tau):
+        return cap.cap_mppi_cost((C.c_double * 4)(3, 3, 10, 0), (C.c_double * 4)(0.6, 0.6, 2, 0),
+                                 (C.c_double * 2)(2, 1), 1000.0, 0.1, 0.0, tau)
+    f = cap._lib.cap_mppi_step
+    assert f(z, z, 4, 0.1, 8, p, p, p, 3, C.byref(grid), C.byref(cost(0.0)), p, None) == \
+        cap.CAP_E_INVALID
+    assert f(z, z, 0, 0.1, 8, p, p, None, 0, None, C.byref(cost(1.0)), p, None) == \
+        cap.CAP_E_INVALID
+    assert f(z, z, 4, 0.1, 8, p, C.c_void_p(264), None, 0, None, C.byref(cost(1.0)), p,
+             None) == cap.CAP_E_INVALID                                   # misaligned delta
+    assert f(z, z, 4, 0.1, 8, p, p, p, 3, None, C.byref(cost(1.0)), p, None) == \
+        cap.CAP_E_INVALID                                                 # occupancy, no grid
