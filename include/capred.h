@@ -250,7 +250,8 @@ typedef struct cap_plan_config {
   int32_t block_threads;        /* 0 = default; else 256, 512 or 1024           */
   int32_t particles_per_thread; /* 0 = default; else 1, 2 or 4                  */
   int32_t lds_bytes;            /* 0 = default; LDS histogram window per block  */
-  int32_t grid_blocks;          /* 0 = default; persistent blocks per launch    */
+  int32_t grid_blocks;          /* 0 = default: fill every CU at each rollout
+                                   variant's occupancy; else persistent blocks */
   int32_t max_smooth_radius;    /* 0 = no smoothing stage; 1..16 = largest radius a
                                    slot may ask for (sizes the stage's LDS tile) */
   int32_t n_speeds;             /* shared control set as in cap_model: 0 = one speed */

@@ -280,7 +280,7 @@ struct cap_plan {
   uint32_t* queues = nullptr;   // ring * 8 tile counters (device)
   size_t entry_bytes = 0;
   int cap_words = 0;            // LDS window words per buffer
-  int grid_blocks = 0;
+  int grid_blocks[2] = {0, 0};  // persistent blocks per launch, per rollout variant
   int smooth_blocks = 0;        // persistent blocks of the smoothing stage (0: no stage)
   int per_tile = 0;
   const void* rollout_fn[2] = {nullptr, nullptr};      // [shift variant]
@@ -345,7 +345,7 @@ static cap_status launch_rollout(cap_plan* p, const Entry& e, int variant, hipSt
   const uint8_t* base = e.dev;
   uint32_t* q = e.queues;
   void* args[] = {(void*)&base, (void*)&q, (void*)&p->cap_words};
-  CAP_HIP(hipLaunchKernel(p->rollout_fn[variant], dim3(p->grid_blocks), dim3(p->cfg.block_threads), args,
+  CAP_HIP(hipLaunchKernel(p->rollout_fn[variant], dim3(p->grid_blocks[variant]), dim3(p->cfg.block_threads), args,
                           window_lds_bytes(p->cap_words, p->per_tile), s));
   return CAP_OK;
 }
@@ -521,22 +521,21 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
     e = hipFuncSetAttribute(p->rollout_fn[v], hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)e;  // not required on gfx950; the occupancy query below validates the size
   }
-  // both variants share the persistent grid: size it for the tighter one
-  int per_cu = 1 << 30;
-  for (int v = 0; v < 2 && e == hipSuccess; ++v) {
-    int pc = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, p->rollout_fn[v], cfg.block_threads, dyn);
-    per_cu = std::min(per_cu, pc);
-  }
-  if (e != hipSuccess || per_cu < 1) {
+  // each variant's persistent grid fills the chip at that variant's own
+  // occupancy (the shifted variant needs more registers)
+  int per_cu[2] = {0, 0};
+  for (int v = 0; v < 2 && e == hipSuccess; ++v)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[v], p->rollout_fn[v],
+                                                     cfg.block_threads, dyn);
+  if (e != hipSuccess || per_cu[0] < 1 || per_cu[1] < 1) {
     destroy_plan(p);
     return e != hipSuccess ? hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor")
                            : fail(CAP_E_INVALID, "LDS window too large for one block per CU");
   }
   const int cus = cap_device_cu_count();
-  if (cfg.grid_blocks == 0) cfg.grid_blocks = std::max(1, cus) * per_cu;
-  p->cfg.grid_blocks = cfg.grid_blocks;
-  p->grid_blocks = cfg.grid_blocks;
+  for (int v = 0; v < 2; ++v)
+    p->grid_blocks[v] = cfg.grid_blocks > 0 ? cfg.grid_blocks : std::max(1, cus) * per_cu[v];
+  p->cfg.grid_blocks = p->grid_blocks[0];
   if (cfg.max_smooth_radius > 0) {
     const size_t sl = smooth_lds_bytes(cfg.max_smooth_radius);
     (void)hipFuncSetAttribute((const void*)plan_smooth_kernel,

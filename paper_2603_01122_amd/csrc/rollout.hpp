@@ -50,18 +50,20 @@ struct Window {
 };
 
 __device__ __forceinline__ Window step_window(const RolloutDesc& d, int t) {
-  Window win;
+  // 64-bit only for the reach t * R (up to 2^36); the shifted bounds fit 32 bits,
+  // so the clamps stay in scalar 32-bit arithmetic
   const int64_t rx = (int64_t)t * d.Rx, ry = (int64_t)t * d.Ry;
-  int64_t lx = floor_shift16((int64_t)d.X0 - rx), hx = floor_shift16((int64_t)d.X0 + rx);
-  int64_t ly = floor_shift16((int64_t)d.Y0 - ry), hy = floor_shift16((int64_t)d.Y0 + ry);
-  lx = lx < 0 ? 0 : lx;
-  ly = ly < 0 ? 0 : ly;
-  hx = hx > d.nx - 1 ? d.nx - 1 : hx;
-  hy = hy > d.ny - 1 ? d.ny - 1 : hy;
-  win.x0 = (int)lx;
-  win.y0 = (int)ly;
-  win.w = hx >= lx ? (int)(hx - lx + 1) : 0;
-  win.h = hy >= ly ? (int)(hy - ly + 1) : 0;
+  int lx = (int)floor_shift16((int64_t)d.X0 - rx), hx = (int)floor_shift16((int64_t)d.X0 + rx);
+  int ly = (int)floor_shift16((int64_t)d.Y0 - ry), hy = (int)floor_shift16((int64_t)d.Y0 + ry);
+  lx = max(lx, 0);
+  ly = max(ly, 0);
+  hx = min(hx, d.nx - 1);
+  hy = min(hy, d.ny - 1);
+  Window win;
+  win.x0 = lx;
+  win.y0 = ly;
+  win.w = hx >= lx ? hx - lx + 1 : 0;
+  win.h = hy >= ly ? hy - ly + 1 : 0;
   return win;
 }
 
@@ -152,7 +154,6 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
 
   const size_t plane = (size_t)d.nx * (size_t)d.ny;
   uint4 rw[P];
-  const int lane = tid & 63;
   const int list_cap = P * nthr;
   uint16_t* lists = reinterpret_cast<uint16_t*>(win + 2 * cap);
   int m3 = 1;  // t mod 3
@@ -212,20 +213,12 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
           off = true;
         }
       }
-      // wave-aggregated append of the freshly touched words
-      const uint64_t fm = __ballot(fresh);
-      if (fm) {
-        const int leader = __ffsll((unsigned long long)fm) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&sh.ntouch[m3], (uint32_t)__popcll(fm));
-        base = __shfl(base, leader, 64);
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-            (uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
-        if (fresh) list[base + below] = (uint16_t)widx;
-      }
+      // append of the freshly touched words and the off-grid count: the
+      // compiler's atomic optimizer turns each uniform-address increment into
+      // one LDS atomic per wavefront plus a lane prefix count
+      if (fresh) list[atomicAdd(&sh.ntouch[m3], 1u)] = (uint16_t)widx;
       off_any |= off;
-      const uint64_t m = __ballot(off);
-      if (m && lane == 0) atomicAdd(&sh.off[t & 1], (uint32_t)__popcll(m));
+      if (off) atomicAdd(&sh.off[t & 1], 1u);
     }
     (void)off_any;
     __syncthreads();
