@@ -7,7 +7,8 @@
 namespace capred {
 
 constexpr int kBeliefThreads = 256;
-constexpr int kBeliefChunk = 16;  // observed transitions staged in LDS at a time
+constexpr int kBeliefChunk = 4;   // observed transitions staged in LDS at a time (8 KiB: the
+                                  // update fits beside the rollout blocks of a busy CU)
 
 struct BeliefShared {
   float ell[kBeliefChunk * CAP_MAX_J];

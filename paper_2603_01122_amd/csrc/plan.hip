@@ -22,7 +22,6 @@ namespace capred {
 
 constexpr int kMaxObs = 8;
 constexpr int kXcds = 8;
-constexpr int kChunk = 8192;  // grid cells per clear/normalise chunk
 
 struct SlotDev {
   RolloutDesc rd;          // rollout of this cycle (start, ring-entry outputs)
@@ -35,13 +34,15 @@ struct SlotDev {
   float obs[(kMaxObs + 1) * 2];
   int32_t smooth_r;        // 0: probs = count / N; > 0: Gaussian-smoothed probs
   SmoothWeights smooth_w;  // normalised 1-D kernel, smooth_w.w[d + smooth_r]
+  int32_t prev_x0, prev_y0;  // start of the previous cycle that wrote this ring entry
+  int32_t full_clear;        // 1: the ring entry's content is unknown (clear every cell)
 };
 
 struct CycleHeader {
   uint32_t seed_lo, seed_hi, cycle;
   int32_t n_active, n_tiles, per_tile;
   int32_t tile_begin[CAP_MAX_SLOTS + 1];
-  int32_t chunk_begin[CAP_MAX_SLOTS + 1];  // prefix of grid chunks (kChunk cells)
+  int32_t step_begin[CAP_MAX_SLOTS + 1];   // prefix of horizons (one work item per step)
   int32_t smooth_begin[CAP_MAX_SLOTS + 1]; // prefix of smoothing tiles
 };
 
@@ -66,17 +67,40 @@ __global__ void __launch_bounds__(kBeliefThreads)
                       sh);
 }
 
-// Grid-sized work (clear, normalise) is cut into chunks of kChunk cells; the
-// chunks of all active humans form one index space (chunk_begin prefix) so
-// that every block streams full chunks whatever the mix of grid sizes.
-__device__ __forceinline__ int slot_of_chunk(const CycleHeader* H, int c) {
-  int lo = 0, hi = H->n_active;  // largest s with chunk_begin[s] <= c
+// Clearing and normalising work only where a ring entry's grids can be
+// nonzero.  After step t every particle lies in the reach window of its start
+// (clipped to the grid), so a ring entry's counts and probabilities are zero
+// outside the window of the cycle that last wrote it; a cycle therefore
+// clears, and afterwards normalises, the bounding box of that window and of
+// its own window (the latter also makes a replayed rollout start from zero).
+// A ring entry whose content is unknown (first use after admission) is done
+// in full.  Work items are the steps of all active humans (step_begin prefix).
+__device__ __forceinline__ int slot_of_step(const CycleHeader* H, int item) {
+  int lo = 0, hi = H->n_active;  // largest s with step_begin[s] <= item
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (H->chunk_begin[mid] <= c) lo = mid;
+    if (H->step_begin[mid] <= item) lo = mid;
     else hi = mid;
   }
   return lo;
+}
+
+__device__ __forceinline__ Window clear_region(const SlotDev& sd, int t) {
+  const RolloutDesc& d = sd.rd;
+  if (sd.full_clear) return Window{0, 0, d.nx, d.ny};
+  const Window a = step_window_at(d, d.X0, d.Y0, t);
+  const Window b = step_window_at(d, sd.prev_x0, sd.prev_y0, t);
+  if (a.w == 0 || a.h == 0) return b;
+  if (b.w == 0 || b.h == 0) return a;
+  const int x0 = min(a.x0, b.x0), y0 = min(a.y0, b.y0);
+  const int x1 = max(a.x0 + a.w, b.x0 + b.w), y1 = max(a.y0 + a.h, b.y0 + b.h);
+  return Window{x0, y0, x1 - x0, y1 - y0};
+}
+
+__device__ __forceinline__ void item_range(const CycleHeader* H, int only, int* i0, int* i1) {
+  const int na = H->n_active;
+  *i0 = only >= 0 ? (only < na ? H->step_begin[only] : 0) : 0;
+  *i1 = only >= 0 ? (only < na ? H->step_begin[only + 1] : 0) : H->step_begin[na];
 }
 
 // Clears the counts (and off-grid counters) of every active slot -- or of one
@@ -86,25 +110,20 @@ __global__ void __launch_bounds__(256)
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
   if (blockIdx.x == 0 && threadIdx.x < kXcds) queues[threadIdx.x] = 0u;
   const SlotDev* sl = slots_of(base);
-  const int na = H->n_active;
-  const int c0 = only >= 0 ? (only < na ? H->chunk_begin[only] : 0) : 0;
-  const int c1 = only >= 0 ? (only < na ? H->chunk_begin[only + 1] : 0) : H->chunk_begin[na];
-  for (int c = c0 + (int)blockIdx.x; c < c1; c += (int)gridDim.x) {
-    const int s = __builtin_amdgcn_readfirstlane(slot_of_chunk(H, c));
-    uint32_t* p = sl[s].rd.counts;
-    const int64_t n = sl[s].n_cells;
-    const int64_t off = (int64_t)(c - H->chunk_begin[s]) * kChunk;
-    const int64_t end = min(off + (int64_t)kChunk, n);
-    if (((reinterpret_cast<uintptr_t>(p + off)) & 15u) == 0) {
-      uint4* p4 = reinterpret_cast<uint4*>(p + off);
-      const int64_t n4 = (end - off) / 4;
-      for (int64_t v = threadIdx.x; v < n4; v += blockDim.x) p4[v] = make_uint4(0u, 0u, 0u, 0u);
-      for (int64_t v = off + n4 * 4 + threadIdx.x; v < end; v += blockDim.x) p[v] = 0u;
-    } else {
-      for (int64_t v = off + threadIdx.x; v < end; v += blockDim.x) p[v] = 0u;
+  int i0, i1;
+  item_range(H, only, &i0, &i1);
+  for (int it = i0 + (int)blockIdx.x; it < i1; it += (int)gridDim.x) {
+    const int s = __builtin_amdgcn_readfirstlane(slot_of_step(H, it));
+    const SlotDev& sd = sl[s];
+    const int t = it - H->step_begin[s] + 1;
+    const Window r = clear_region(sd, t);
+    uint32_t* p = sd.rd.counts + (size_t)(t - 1) * sd.rd.nx * sd.rd.ny;
+    const int n = r.w * r.h;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int y = i / r.w, x = i - y * r.w;
+      p[(size_t)(r.y0 + y) * sd.rd.nx + r.x0 + x] = 0u;
     }
-    if (off == 0 && sl[s].rd.offgrid)
-      for (int v = threadIdx.x; v < sl[s].rd.H; v += blockDim.x) sl[s].rd.offgrid[v] = 0u;
+    if (threadIdx.x == 0 && sd.rd.offgrid) sd.rd.offgrid[t - 1] = 0u;
   }
 }
 
@@ -112,37 +131,23 @@ __global__ void __launch_bounds__(256)
     plan_normalize_kernel(const uint8_t* __restrict__ base, int only) {
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
   const SlotDev* sl = slots_of(base);
-  const int na = H->n_active;
-  const int c0 = only >= 0 ? (only < na ? H->chunk_begin[only] : 0) : 0;
-  const int c1 = only >= 0 ? (only < na ? H->chunk_begin[only + 1] : 0) : H->chunk_begin[na];
-  for (int c = c0 + (int)blockIdx.x; c < c1; c += (int)gridDim.x) {
-    const int s = __builtin_amdgcn_readfirstlane(slot_of_chunk(H, c));
-    float* p = sl[s].probs;
-    if (!p || sl[s].smooth_r > 0) continue;
-    const uint32_t* q = sl[s].rd.counts;
-    const float N = (float)sl[s].rd.N;
-    const int64_t n = sl[s].n_cells;
-    const int64_t off = (int64_t)(c - H->chunk_begin[s]) * kChunk;
-    const int64_t end = min(off + (int64_t)kChunk, n);
-    if (((reinterpret_cast<uintptr_t>(q + off) | reinterpret_cast<uintptr_t>(p + off)) & 15u) == 0) {
-      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-      typedef float f32x4 __attribute__((ext_vector_type(4)));
-      const u32x4* q4 = reinterpret_cast<const u32x4*>(q + off);
-      f32x4* p4 = reinterpret_cast<f32x4*>(p + off);
-      const int64_t n4 = (end - off) / 4;
-      for (int64_t v = threadIdx.x; v < n4; v += blockDim.x) {
-        const u32x4 x = __builtin_nontemporal_load(q4 + v);
-        f32x4 y;
-        y.x = (float)x.x / N;
-        y.y = (float)x.y / N;
-        y.z = (float)x.z / N;
-        y.w = (float)x.w / N;
-        __builtin_nontemporal_store(y, p4 + v);
-      }
-      for (int64_t v = off + n4 * 4 + threadIdx.x; v < end; v += blockDim.x)
-        p[v] = (float)q[v] / N;
-    } else {
-      for (int64_t v = off + threadIdx.x; v < end; v += blockDim.x) p[v] = (float)q[v] / N;
+  int i0, i1;
+  item_range(H, only, &i0, &i1);
+  for (int it = i0 + (int)blockIdx.x; it < i1; it += (int)gridDim.x) {
+    const int s = __builtin_amdgcn_readfirstlane(slot_of_step(H, it));
+    const SlotDev& sd = sl[s];
+    if (!sd.probs || sd.smooth_r > 0) continue;
+    const int t = it - H->step_begin[s] + 1;
+    const Window r = clear_region(sd, t);
+    const size_t plane = (size_t)(t - 1) * sd.rd.nx * sd.rd.ny;
+    const uint32_t* q = sd.rd.counts + plane;
+    float* p = sd.probs + plane;
+    const float N = (float)sd.rd.N;
+    const int n = r.w * r.h;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int y = i / r.w, x = i - y * r.w;
+      const size_t c = (size_t)(r.y0 + y) * sd.rd.nx + r.x0 + x;
+      p[c] = (float)q[c] / N;
     }
   }
 }
@@ -256,6 +261,8 @@ struct HostSlot {
   int n_staged = 0;
   float staged[kMaxObs * 2];
   bool reset = false;
+  int32_t ent_x0[4] = {0, 0, 0, 0}, ent_y0[4] = {0, 0, 0, 0};  // last start per ring entry
+  bool ent_full[4] = {true, true, true, true};                 // ring entry content unknown
 };
 
 struct Entry {
@@ -407,7 +414,7 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
   H->seed_hi = (uint32_t)(seed >> 32);
   H->cycle = cycle;
   H->per_tile = p->per_tile;
-  int n = 0, tiles = 0, chunks = 0, sblocks = 0, variant = 0;
+  int n = 0, tiles = 0, steps_total = 0, sblocks = 0, variant = 0;
   int64_t parts = 0, steps = 0;
   for (auto& hs : p->slots) {
     if (!hs.active) continue;
@@ -436,11 +443,17 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
     // the rollout starts from the newest observed position (validated at staging)
     sd.rd.X0 = (int32_t)lattice_coord((double)hs.last[0], hs.grid.x0, hs.grid.cell);
     sd.rd.Y0 = (int32_t)lattice_coord((double)hs.last[1], hs.grid.y0, hs.grid.cell);
+    sd.prev_x0 = hs.ent_x0[re];
+    sd.prev_y0 = hs.ent_y0[re];
+    sd.full_clear = hs.ent_full[re] ? 1 : 0;
+    hs.ent_x0[re] = sd.rd.X0;
+    hs.ent_y0[re] = sd.rd.Y0;
+    hs.ent_full[re] = false;
     H->tile_begin[n] = tiles;
-    H->chunk_begin[n] = chunks;
+    H->step_begin[n] = steps_total;
     H->smooth_begin[n] = sblocks;
     tiles += (int)((sd.rd.N + p->per_tile - 1) / p->per_tile);
-    chunks += (int)((hs.n_cells + kChunk - 1) / kChunk);
+    steps_total += sd.rd.H;
     if (sd.smooth_r > 0 && sd.probs)
       sblocks += sd.rd.H * ((sd.rd.ny + kBandRows - 1) / kBandRows) *
                  ((sd.rd.nx + kSmoothThreads - 1) / kSmoothThreads);
@@ -449,7 +462,7 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
     ++n;
   }
   H->tile_begin[n] = tiles;
-  H->chunk_begin[n] = chunks;
+  H->step_begin[n] = steps_total;
   H->smooth_begin[n] = sblocks;
   H->n_active = n;
   p->last_variant = variant;
@@ -726,8 +739,7 @@ extern "C" cap_status cap_plan_run_plain(cap_plan* p, uint64_t seed, uint32_t cy
   for (int i = 0; i < H->n_active; ++i) {
     hipLaunchKernelGGL(plan_update_kernel, dim3(1), dim3(kBeliefThreads), 0, s, base, i);
     if (i == H->n_active - 1) CAP_HIP(hipEventRecord(p->ev_update, s));
-    const size_t n = (size_t)sl[i].n_cells;
-    const unsigned zb = (unsigned)std::min<size_t>((n + kChunk - 1) / kChunk, 2048);
+    const unsigned zb = (unsigned)std::min(sl[i].rd.H, 2048);
     hipLaunchKernelGGL(plan_zero_kernel, dim3(zb), dim3(256), 0, s, base, en.queues, i);
     const int tiles = H->tile_begin[i + 1] - H->tile_begin[i];
     int si = i;
@@ -735,7 +747,7 @@ extern "C" cap_status cap_plan_run_plain(cap_plan* p, uint64_t seed, uint32_t cy
     CAP_HIP(hipLaunchKernel(p->rollout_one_fn[sl[i].rd.shift ? 1 : 0], dim3(tiles), dim3(p->cfg.block_threads), args,
                             window_lds_bytes(p->cap_words, p->per_tile), s));
     if (sl[i].probs && sl[i].smooth_r == 0) {
-      const unsigned nb = (unsigned)std::min<size_t>((n + kChunk - 1) / kChunk, 4096);
+      const unsigned nb = (unsigned)std::min(sl[i].rd.H, 4096);
       hipLaunchKernelGGL(plan_normalize_kernel, dim3(nb), dim3(256), 0, s, base, i);
     }
     if (sl[i].probs && sl[i].smooth_r > 0) {

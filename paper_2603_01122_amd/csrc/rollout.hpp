@@ -49,12 +49,14 @@ struct Window {
   int x0, y0, w, h;
 };
 
-__device__ __forceinline__ Window step_window(const RolloutDesc& d, int t) {
+// Reach window of step t for a start (X0, Y0) on the lattice.
+__device__ __forceinline__ Window step_window_at(const RolloutDesc& d, int32_t X0, int32_t Y0,
+                                                 int t) {
   // 64-bit only for the reach t * R (up to 2^36); the shifted bounds fit 32 bits,
   // so the clamps stay in scalar 32-bit arithmetic
   const int64_t rx = (int64_t)t * d.Rx, ry = (int64_t)t * d.Ry;
-  int lx = (int)floor_shift16((int64_t)d.X0 - rx), hx = (int)floor_shift16((int64_t)d.X0 + rx);
-  int ly = (int)floor_shift16((int64_t)d.Y0 - ry), hy = (int)floor_shift16((int64_t)d.Y0 + ry);
+  int lx = (int)floor_shift16((int64_t)X0 - rx), hx = (int)floor_shift16((int64_t)X0 + rx);
+  int ly = (int)floor_shift16((int64_t)Y0 - ry), hy = (int)floor_shift16((int64_t)Y0 + ry);
   lx = max(lx, 0);
   ly = max(ly, 0);
   hx = min(hx, d.nx - 1);
@@ -65,6 +67,10 @@ __device__ __forceinline__ Window step_window(const RolloutDesc& d, int t) {
   win.w = hx >= lx ? hx - lx + 1 : 0;
   win.h = hy >= ly ? hy - ly + 1 : 0;
   return win;
+}
+
+__device__ __forceinline__ Window step_window(const RolloutDesc& d, int t) {
+  return step_window_at(d, d.X0, d.Y0, t);
 }
 
 __device__ __forceinline__ uint32_t pick_word(const uint4& w, int s) {

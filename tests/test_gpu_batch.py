@@ -291,3 +291,31 @@ def test_plan_errors(cap):
     p.run(0, 0)
     p.sync()
     p.close()
+
+
+def test_replay_reproduces_the_cycle(orc, cap):
+    """Re-running the latest rollout alone (the benchmark's kernel timing)
+    recomputes the same grids: the clear covers both the previous and the new
+    reach windows."""
+    humans = small_scene(n=4, N_div=8, H=30)
+    tr = tracks_for(orc, humans, 6)
+    srv = make_server(cap, humans)
+    for h in humans:
+        srv.submit(request(cap, h, tr[h.hid][0]))
+    note("replay of the latest rollout")
+    for c in range(4):
+        srv.step({h.hid: tr[h.hid][c + 1] for h in humans})
+    srv.drain()
+    torch.cuda.synchronize()
+    before = {h.hid: snapshot(srv, h.hid, 3) for h in humans}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    e1.record()
+    for _ in range(3):
+        srv.plan.replay_rollout(torch.cuda.current_stream(), e0, e1)
+    torch.cuda.synchronize()
+    for h in humans:
+        after = snapshot(srv, h.hid, 3)
+        assert np.array_equal(after[0], before[h.hid][0])
+        assert np.array_equal(after[2], before[h.hid][2])
+    srv.close()
