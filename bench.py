@@ -393,6 +393,9 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
                 "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": profiled_traffic(best),
+                # the same work per back-to-back cycle (consecutive rollouts overlap
+                # their tails on the two streams): a serving-throughput view
+                "cycle_frac": round(W * psteps / sec_per_cycle / PEAK_LANE_OPS, 4),
                 "kernel": "plan_rollout_kernel", "ms_per_launch": round(roll * 1e3, 4),
                 "ops_per_particle_step": round(W, 2),
                 "particle_steps_per_launch": psteps,
