@@ -105,10 +105,11 @@ def make_server(capred, humans, tuning, tracks):
     return srv
 
 
-def cpu_baseline(scene, max_seconds):
-    """The FP64 oracle on one full serving cycle (belief update + Alg. 1 for all
-    humans), on every host core this process may use.  Its observations come
-    from its own track simulator."""
+def cpu_baseline(scene, max_seconds, min_seconds=10.0):
+    """The FP64 oracle on whole serving cycles (belief update with the newest
+    observation + Alg. 1 for all humans), on every host core this process may
+    use, for at least min_seconds (whole cycles, at most max_seconds).  Its
+    observations come from its own track simulator."""
     import numpy as np
     import oracle
     threads = oracle.default_threads()
@@ -116,27 +117,36 @@ def cpu_baseline(scene, max_seconds):
     for h in scene.humans:
         _, pos = oracle.simulate_tracks(K=h.K, speed=h.speed, dt=h.dt, frame=h.frame,
                                         start=np.array([h.start]), beta=[h.true_beta],
-                                        goal=h.goals[h.true_goal][None], T=1, seed=0,
+                                        goal=h.goals[h.true_goal][None], T=64, seed=0,
                                         stream=h.hid)
         sims[h.hid] = pos[0]
+    lb = {h.hid: None for h in scene.humans}
     t0 = time.perf_counter()
     steps = 0
-    done = 0
-    for h in scene.humans:
-        obs = sims[h.hid]
-        _, b, _ = oracle.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals,
-                                       obs=obs)
-        oracle.predict(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals, grid=h.grid,
-                       z0=tuple(obs[-1].astype(float)), belief=b, N=h.N, H=h.H, seed=0,
-                       human=h.hid, cycle=0, nthreads=threads)
-        steps += h.N * h.H
-        done += 1
+    cycles = 0
+    humans_done = 0
+    while cycles < 63:
+        for h in scene.humans:
+            obs = sims[h.hid][cycles:cycles + 2]
+            lb[h.hid], b, _ = oracle.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta,
+                                                   goals=h.goals, obs=obs, log_belief=lb[h.hid])
+            oracle.predict(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals, grid=h.grid,
+                           z0=tuple(obs[-1].astype(float)), belief=b, N=h.N, H=h.H, seed=0,
+                           human=h.hid, cycle=cycles, nthreads=threads)
+            steps += h.N * h.H
+            humans_done += 1
+            if time.perf_counter() - t0 > max_seconds:
+                break
         if time.perf_counter() - t0 > max_seconds:
             break
+        cycles += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
     dt = time.perf_counter() - t0
-    sample = (f"one full serving cycle of the 16-human workload ({done} humans, "
-              f"{steps} particle-steps)" if done == len(scene.humans) else
-              f"{done} of {len(scene.humans)} humans of one cycle ({steps} particle-steps)")
+    n_h = len(scene.humans)
+    sample = (f"{cycles} full serving cycles of the {n_h}-human workload "
+              f"({steps} particle-steps)" if humans_done == cycles * n_h else
+              f"{humans_done} human-cycles of the {n_h}-human workload ({steps} particle-steps)")
     return {"value": steps / dt, "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
 
@@ -228,6 +238,21 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
         roll = float(np.mean(durs))
     finally:
         srv.close()
+    # the per-human reference launches of the same scene (one warm cycle, then timed ones)
+    plain_shape = tune.shipped(humans, plain=True) or {"block_threads": 512,
+                                                       "particles_per_thread": 1}
+    psrv = make_server(capred, humans, plain_shape, tracks)
+    try:
+        psrv.step({h.hid: tracks[h.hid][1] for h in humans}, plain=True)
+        psrv.drain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in range(1, 1 + cycles):
+            psrv.step({h.hid: tracks[h.hid][c + 1] for h in humans}, plain=True)
+        torch.cuda.synchronize()
+        plain_sec = (time.perf_counter() - t0) / cycles
+    finally:
+        psrv.close()
     psteps = sc.particle_steps
     W = algorithmic_ops(humans[0].K, rates)
     achieved = W * psteps / roll
@@ -235,7 +260,9 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
                         "dt=0.01 s, H=200, 512x512 grids at 0.02 m",
             "particle_steps_per_cycle": psteps, "cycles": cycles,
             "ms_per_cycle": round(sec * 1e3, 3), "value": float(f"{psteps / sec:.6e}"),
-            "tuning": shape,
+            "plain_ms_per_cycle": round(plain_sec * 1e3, 3),
+            "batched_over_plain": round(plain_sec / sec, 3),
+            "tuning": shape, "plain_tuning": plain_shape,
             "roofline": {"bound": "alu", "kernel": "plan_rollout_kernel",
                          "ms_per_launch": round(roll * 1e3, 3),
                          "ops_per_particle_step": round(W, 2),
@@ -439,7 +466,8 @@ def main():
         log("largest scene: 64 humans x 2^20 particles, K=32, H=200")
         largest = largest_scene(capred, torch, np, tune, scenes, rates, args.largest_cycles)
         log(f"  {largest['ms_per_cycle']} ms/cycle, {largest['value']:.3e} particle-steps/s, "
-            f"rollout frac {largest['roofline']['frac']}")
+            f"rollout frac {largest['roofline']['frac']}, plain {largest['plain_ms_per_cycle']} "
+            f"ms/cycle ({largest['batched_over_plain']}x)")
 
     tab1 = None
     if not args.no_tab1:
@@ -449,7 +477,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, one full cycle)")
+        log("cpu baseline (oracle, whole cycles for at least 10 s)")
         cpu = cpu_baseline(scene, args.cpu_seconds)
 
     latency = None
