@@ -102,6 +102,24 @@ __device__ __forceinline__ double uniform24d(uint32_t w) {
   return (double)((w >> 9) * 2u + 1u) * 5.9604644775390625e-8;
 }
 
+// Global-memory (address space 1) view of a generic pointer.  Pointers that a
+// kernel loads from descriptor tables in device memory are generic to the
+// compiler, which then emits FLAT accesses; a FLAT access also counts on the
+// LDS wait counter, so every later LDS wait (each barrier, each LDS atomic
+// whose result is used) would wait for its round trip to memory.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(T* p) {
+  return (global_ptr<T>)p;
+}
+
+// Relaxed device-scope integer add through the global path (no return value).
+__device__ __forceinline__ void global_add(uint32_t* p, uint32_t v) {
+  __hip_atomic_fetch_add(as_global(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }

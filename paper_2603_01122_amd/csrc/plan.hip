@@ -3,13 +3,18 @@
 // clear and the normalisation in hipGraphs (one pair per ring entry), with
 // per-cycle descriptors refreshed by a single host-to-device copy.
 //
-// Scheduling: the tiles of all humans (P * blockDim particles each) form one
-// index space split into 8 contiguous ranges, one per XCD; block b starts on
-// the range of XCD (b mod 8) -- workgroups are dispatched round-robin over the
-// XCDs -- so that the tiles of one human share that XCD's L2, and steals from
-// the other ranges when its own is exhausted.  Every cycle's results depend
-// only on (human id, cycle, seed), never on the slot or the tile order:
-// histogram updates are integer atomics.
+// Scheduling: the particles of every human are cut into tiles of three sizes
+// (P, P/2 and P/4 particles per thread).  Each kind's tiles are dealt evenly
+// to 8 queues, one per XCD (workgroups are dispatched round-robin over the
+// XCDs, so block b starts on queue b mod 8), and each queue hands out its big
+// tiles first, then its halves, then its quarters; a block whose queue is
+// empty takes from the next ones.  The host sizes the split per cycle so that,
+// after whole rounds of big tiles on every resident block, the rest is spread
+// as evenly as the tile sizes allow over the CUs: the blocks finish together
+// instead of a few CUs running a last round of big tiles while the rest of the
+// chip idles.  Every cycle's results depend only on (human id, cycle, seed),
+// never on the slot, the tile sizes or the tile order: histogram updates are
+// integer atomics.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +27,8 @@ namespace capred {
 
 constexpr int kMaxObs = 8;
 constexpr int kXcds = 8;
+constexpr int kQueueWords = kXcds;   // tile counters per ring entry, one per XCD
+constexpr int kTileKinds = 3;    // P, P/2, P/4 particles per thread
 
 struct SlotDev {
   RolloutDesc rd;          // rollout of this cycle (start, ring-entry outputs)
@@ -36,12 +43,15 @@ struct SlotDev {
   SmoothWeights smooth_w;  // normalised 1-D kernel, smooth_w.w[d + smooth_r]
   int32_t prev_x0, prev_y0;  // start of the previous cycle that wrote this ring entry
   int32_t full_clear;        // 1: the ring entry's content is unknown (clear every cell)
+  int32_t kt_begin[kTileKinds];  // per tile kind: tickets of earlier slots (within the kind)
+  int32_t kt_first[kTileKinds];  // per tile kind: first particle of this slot's tiles
 };
 
 struct CycleHeader {
   uint32_t seed_lo, seed_hi, cycle;
   int32_t n_active, n_tiles, per_tile;
-  int32_t tile_begin[CAP_MAX_SLOTS + 1];
+  int32_t kind_begin[kTileKinds + 1];      // ticket ranges of the three tile kinds
+  int32_t tile_begin[CAP_MAX_SLOTS + 1];   // per-human launches: prefix of P-sized tiles
   int32_t step_begin[CAP_MAX_SLOTS + 1];   // prefix of horizons (one work item per step)
   int32_t smooth_begin[CAP_MAX_SLOTS + 1]; // prefix of smoothing tiles
 };
@@ -108,7 +118,7 @@ __device__ __forceinline__ void item_range(const CycleHeader* H, int only, int* 
 __global__ void __launch_bounds__(256)
     plan_zero_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int only) {
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
-  if (blockIdx.x == 0 && threadIdx.x < kXcds) queues[threadIdx.x] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < kQueueWords) queues[threadIdx.x] = 0u;
   const SlotDev* sl = slots_of(base);
   int i0, i1;
   item_range(H, only, &i0, &i1);
@@ -117,13 +127,13 @@ __global__ void __launch_bounds__(256)
     const SlotDev& sd = sl[s];
     const int t = it - H->step_begin[s] + 1;
     const Window r = clear_region(sd, t);
-    uint32_t* p = sd.rd.counts + (size_t)(t - 1) * sd.rd.nx * sd.rd.ny;
+    global_ptr<uint32_t> p = as_global(sd.rd.counts) + (size_t)(t - 1) * sd.rd.nx * sd.rd.ny;
     const int n = r.w * r.h;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       const int y = i / r.w, x = i - y * r.w;
       p[(size_t)(r.y0 + y) * sd.rd.nx + r.x0 + x] = 0u;
     }
-    if (threadIdx.x == 0 && sd.rd.offgrid) sd.rd.offgrid[t - 1] = 0u;
+    if (threadIdx.x == 0 && sd.rd.offgrid) as_global(sd.rd.offgrid)[t - 1] = 0u;
   }
 }
 
@@ -187,11 +197,15 @@ __global__ void __launch_bounds__(kSmoothThreads)
   }
 }
 
-__device__ __forceinline__ int slot_of_tile(const CycleHeader* H, int tile) {
-  int lo = 0, hi = H->n_active;  // largest s with tile_begin[s] <= tile
+// Slot of ticket `local` within tile kind k: the largest s whose kind-k
+// tickets start at or before it (slots without such tiles share the next
+// slot's start and are skipped by "largest").
+__device__ __forceinline__ int slot_of_kind_tile(const SlotDev* sl, int n_active, int k,
+                                                 int local) {
+  int lo = 0, hi = n_active;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (H->tile_begin[mid] <= tile) lo = mid;
+    if (sl[mid].kt_begin[k] <= local) lo = mid;
     else hi = mid;
   }
   return lo;
@@ -202,34 +216,61 @@ __global__ void __launch_bounds__(1024)
     plan_rollout_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int cap) {
   __shared__ TileShared sh;
   __shared__ float4 ctl[MS ? CAP_MAX_U : 1];
-  __shared__ int s_tile;
+  __shared__ int s_tile[2];
   extern __shared__ uint32_t win[];
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
   const SlotDev* sl = slots_of(base);
   for (int i = threadIdx.x; i < 2 * cap; i += blockDim.x) win[i] = 0u;
-  const int n_tiles = H->n_tiles;
   const int home = blockIdx.x % kXcds;
   for (;;) {
     if (threadIdx.x == 0) {
-      int t = -1;
-      for (int k = 0; k < kXcds && t < 0; ++k) {
-        const int q = (home + k) % kXcds;
-        const int lo = (int)(((int64_t)n_tiles * q) / kXcds);
-        const int hi = (int)(((int64_t)n_tiles * (q + 1)) / kXcds);
-        if (lo >= hi) continue;
-        const uint32_t got = atomicAdd(queues + q, 1u);
-        if ((int64_t)lo + got < hi) t = lo + (int)got;
+      // queue q holds, of each kind k, the kind's tiles [n_k q / 8, n_k (q + 1) / 8)
+      int kind = -1, local = 0;
+      for (int i = 0; i < kXcds && kind < 0; ++i) {
+        const int q = (home + i) % kXcds;
+        int lo[kTileKinds], size = 0;
+        for (int k = 0; k < kTileKinds; ++k) {
+          const int nk = H->kind_begin[k + 1] - H->kind_begin[k];
+          lo[k] = (int)(((int64_t)nk * q) / kXcds);
+          size += (int)(((int64_t)nk * (q + 1)) / kXcds) - lo[k];
+        }
+        if (size == 0) continue;
+        int j = (int)atomicAdd(queues + q, 1u);
+        if (j >= size) continue;
+        for (int k = 0; k < kTileKinds; ++k) {
+          const int nk = H->kind_begin[k + 1] - H->kind_begin[k];
+          const int cnt = (int)(((int64_t)nk * (q + 1)) / kXcds) - lo[k];
+          if (j < cnt) {
+            kind = k;
+            local = lo[k] + j;
+            break;
+          }
+          j -= cnt;
+        }
       }
-      s_tile = t;
+      s_tile[0] = kind;
+      s_tile[1] = local;
     }
     __syncthreads();
-    const int tile = __builtin_amdgcn_readfirstlane(s_tile);
-    if (tile < 0) break;
-    const int s = __builtin_amdgcn_readfirstlane(slot_of_tile(H, tile));
-    const int64_t first = (int64_t)(tile - H->tile_begin[s]) * H->per_tile;
+    const int kind = __builtin_amdgcn_readfirstlane(s_tile[0]);
+    if (kind < 0) break;
+    const int local = __builtin_amdgcn_readfirstlane(s_tile[1]);
+    const int s = __builtin_amdgcn_readfirstlane(slot_of_kind_tile(sl, H->n_active, kind, local));
+    const int per = (int)blockDim.x * (P >> kind);
+    const int64_t first = sl[s].kt_first[kind] + (int64_t)(local - sl[s].kt_begin[kind]) * per;
     // rollout_tile starts and ends with a barrier: s_tile is not rewritten
-    // before every thread has read it.
-    rollout_tile<KT, P, SHIFT, MS>(sl[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap, ctl);
+    // before every thread has read it.  The host only makes kinds whose size
+    // P >> kind is at least one particle per thread.
+    if (kind == 0) {
+      rollout_tile<KT, P, SHIFT, MS>(sl[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap, ctl);
+    } else if constexpr (P >= 2) {
+      if (kind == 1 || P == 2)
+        rollout_tile<KT, P / 2, SHIFT, MS>(sl[s].rd, first, H->seed_lo, H->seed_hi, sh, win, cap,
+                                           ctl);
+      else
+        rollout_tile<KT, (P >= 4 ? P / 4 : 1), SHIFT, MS>(sl[s].rd, first, H->seed_lo,
+                                                          H->seed_hi, sh, win, cap, ctl);
+    }
   }
 }
 
@@ -266,7 +307,7 @@ struct HostSlot {
 };
 
 struct Entry {
-  uint32_t* queues = nullptr;   // this entry's 8 tile counters (device)
+  uint32_t* queues = nullptr;   // this entry's tile counter (device)
   uint8_t* dev = nullptr;       // header + slots
   uint8_t* host = nullptr;      // pinned mirror
   hipGraphExec_t upd = nullptr;
@@ -284,10 +325,11 @@ struct cap_plan {
   cap_plan_config cfg;
   std::vector<capred::HostSlot> slots;
   std::vector<capred::Entry> ring;
-  uint32_t* queues = nullptr;   // ring * 8 tile counters (device)
+  uint32_t* queues = nullptr;   // one tile counter per ring entry (device)
   size_t entry_bytes = 0;
   int cap_words = 0;            // LDS window words per buffer
   int grid_blocks[2] = {0, 0};  // persistent blocks per launch, per rollout variant
+  int n_cus = 1;                // compute units of the device
   int smooth_blocks = 0;        // persistent blocks of the smoothing stage (0: no stage)
   int per_tile = 0;
   const void* rollout_fn[2] = {nullptr, nullptr};      // [shift variant]
@@ -405,6 +447,85 @@ static void destroy_plan(cap_plan* p) {
   delete p;
 }
 
+// Cuts the active slots' particles into the three tile kinds of the persistent
+// launch.  Work is counted in units of blockDim particles (a human of N
+// particles has ceil(N / blockDim) units; its last unit may be partial); a
+// kind-k tile holds P >> k units.  With R resident blocks on C CUs and U units
+// in all, whole rounds of big tiles (one per block) take the first
+// P R floor(U / (P R)) units.  The remainder Ur is spread over the CUs, one
+// tile per CU at a time, largest first: one big tile per CU while Ur exceeds
+// 4 C; then, for what is left, quarters (Ur <= C), halves and quarters
+// (Ur <= 2 C) or big tiles and halves (Ur <= 4 C), with as many tiles as CUs
+// (or fewer).  A tile that ends up alone on its CU runs faster than one of a
+// pair, so the last tiles even out the CUs rather than the blocks.  Each
+// human's units that do not fill a big tile become its own smaller tiles; big
+// tiles of the last humans are then split until the targets are met.
+// cnt[s][k] is the number of kind-k tiles of slot s.
+static void split_tiles(const int32_t* units, int n, int P, int R, int C,
+                        int32_t (*cnt)[kTileKinds]) {
+  int64_t U = 0;
+  for (int i = 0; i < n; ++i) U += units[i];
+  int64_t t_half = 0, t_quarter = 0;   // targets (tiles)
+  C = std::max(1, std::min(C, R));
+  if (P >= 4) {
+    int64_t Ur = U % ((int64_t)P * R);
+    if (Ur > 4 * (int64_t)C) Ur -= 4 * (int64_t)C;
+    if (Ur == 0) {
+    } else if (Ur <= C) {
+      t_quarter = Ur;
+    } else if (Ur <= 2 * (int64_t)C) {
+      t_half = Ur - C;
+      t_quarter = 2 * (int64_t)C - Ur;
+    } else {
+      const int64_t big = (Ur - 2 * (int64_t)C + 1) / 2;
+      t_half = (Ur - 4 * big) / 2;
+      t_quarter = Ur - 4 * big - 2 * t_half;
+    }
+  } else if (P == 2) {
+    // kind 1 is the one-unit tile
+    int64_t Ur = U % (2 * (int64_t)R);
+    if (Ur > 2 * (int64_t)C) Ur -= 2 * (int64_t)C;
+    if (Ur <= C) t_half = Ur;
+    else t_half = 2 * (int64_t)C - Ur;
+  }
+  int64_t have_half = 0, have_quarter = 0;
+  for (int i = 0; i < n; ++i) {
+    const int u = units[i];
+    cnt[i][0] = u / P;
+    const int rem = u - cnt[i][0] * P;
+    if (P >= 4) {
+      cnt[i][1] = rem / 2;
+      cnt[i][2] = rem & 1;
+    } else {
+      cnt[i][1] = rem;   // P == 2: rem is 0 or 1 one-unit tiles; P == 1: 0
+      cnt[i][2] = 0;
+    }
+    have_half += cnt[i][1];
+    have_quarter += cnt[i][2];
+  }
+  int64_t need_half = t_half - have_half, need_quarter = t_quarter - have_quarter;
+  for (int i = n - 1; i >= 0 && (need_half > 0 || need_quarter > 0); --i) {
+    while (cnt[i][0] > 0 && (need_half > 0 || need_quarter > 0)) {
+      --cnt[i][0];
+      if (P == 2) {
+        cnt[i][1] += 2;
+        need_half -= 2;
+      } else if (need_half >= 2) {
+        cnt[i][1] += 2;
+        need_half -= 2;
+      } else if (need_half == 1) {
+        cnt[i][1] += 1;
+        cnt[i][2] += 2;
+        need_half -= 1;
+        need_quarter -= 2;
+      } else {
+        cnt[i][2] += 4;
+        need_quarter -= 4;
+      }
+    }
+  }
+}
+
 // Fills ring entry e's host mirror from the active slots; returns its size.
 static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
   uint8_t* hostp = p->ring[e].host;
@@ -466,10 +587,37 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
   H->smooth_begin[n] = sblocks;
   H->n_active = n;
   p->last_variant = variant;
-  H->n_tiles = tiles;
+  // tile kinds of the persistent launch
+  {
+    const int nthr = p->cfg.block_threads, P = p->cfg.particles_per_thread;
+    std::vector<int32_t> units(n);
+    std::vector<int32_t> flat((size_t)n * kTileKinds);
+    int32_t(*cnt)[kTileKinds] = reinterpret_cast<int32_t(*)[kTileKinds]>(flat.data());
+    for (int i = 0; i < n; ++i) units[i] = (int32_t)((out[i].rd.N + nthr - 1) / nthr);
+    split_tiles(units.data(), n, P, std::max(1, p->grid_blocks[variant]), p->n_cus, cnt);
+    int32_t kb = 0;
+    for (int k = 0; k < kTileKinds; ++k) {
+      H->kind_begin[k] = kb;
+      int32_t in_kind = 0;
+      for (int i = 0; i < n; ++i) {
+        out[i].kt_begin[k] = in_kind;
+        in_kind += cnt[i][k];
+      }
+      kb += in_kind;
+    }
+    H->kind_begin[kTileKinds] = kb;
+    for (int i = 0; i < n; ++i) {
+      int32_t first = 0;
+      for (int k = 0; k < kTileKinds; ++k) {
+        out[i].kt_first[k] = first;
+        first += cnt[i][k] * nthr * std::max(1, P >> k);
+      }
+    }
+    H->n_tiles = kb;
+    p->tiles = kb;
+  }
   p->particles = parts;
   p->psteps = steps;
-  p->tiles = tiles;
   return header_bytes(n);
 }
 
@@ -546,6 +694,7 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
                            : fail(CAP_E_INVALID, "LDS window too large for one block per CU");
   }
   const int cus = cap_device_cu_count();
+  p->n_cus = std::max(1, cus);
   for (int v = 0; v < 2; ++v)
     p->grid_blocks[v] = cfg.grid_blocks > 0 ? cfg.grid_blocks : std::max(1, cus) * per_cu[v];
   p->cfg.grid_blocks = p->grid_blocks[0];
@@ -573,9 +722,9 @@ extern "C" cap_status cap_plan_create(const cap_plan_config* cfg_in, cap_plan** 
       return hip_fail(he, #call);           \
     }                                       \
   } while (0)
-  CAP_TRY(hipMalloc(&p->queues, (size_t)cfg.ring * kXcds * sizeof(uint32_t)));
-  CAP_TRY(hipMemset(p->queues, 0, (size_t)cfg.ring * kXcds * sizeof(uint32_t)));
-  for (int e = 0; e < cfg.ring; ++e) p->ring[e].queues = p->queues + (size_t)e * kXcds;
+  CAP_TRY(hipMalloc(&p->queues, (size_t)cfg.ring * kQueueWords * sizeof(uint32_t)));
+  CAP_TRY(hipMemset(p->queues, 0, (size_t)cfg.ring * kQueueWords * sizeof(uint32_t)));
+  for (int e = 0; e < cfg.ring; ++e) p->ring[e].queues = p->queues + (size_t)e * kQueueWords;
   CAP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   CAP_TRY(hipEventCreateWithFlags(&p->ev_update, hipEventDisableTiming));
   for (auto& en : p->ring) {

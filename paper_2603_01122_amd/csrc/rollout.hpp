@@ -105,7 +105,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     double acc = 0.0;
     int last = 0;
     for (int j = 0; j < J; ++j) {
-      const double b = d.belief[j];
+      const double b = as_global(d.belief)[j];
       acc += b;
       sh.P[j] = acc;
       if (b > 0.0) last = j;
@@ -154,7 +154,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
       GXp[p] = sh.goal[g].x;
       GYp[p] = sh.goal[g].y;
       ib[p] = sh.ibeta[b];
-      if (d.trace_pair) d.trace_pair[idx[p]] = j;
+      if (d.trace_pair) as_global(d.trace_pair)[idx[p]] = j;
     }
   }
 
@@ -205,7 +205,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
       bool fresh = false;     // this lane turned an empty window word non-empty
       uint32_t widx = 0;
       if (act[p]) {
-        if (d.trace_k) d.trace_k[(size_t)idx[p] * d.H + (t - 1)] = (uint8_t)k;
+        if (d.trace_k) as_global(d.trace_k)[(size_t)idx[p] * d.H + (t - 1)] = (uint8_t)k;
         const int cx = X[p] >> kLatticeShift, cy = Y[p] >> kLatticeShift;
         if ((unsigned)cx < (unsigned)d.nx && (unsigned)cy < (unsigned)d.ny) {
           const unsigned lx = (unsigned)(cx - wd.x0), ly = (unsigned)(cy - wd.y0);
@@ -213,7 +213,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
             widx = ly * half_w + (lx >> 1);
             fresh = atomicAdd(buf + widx, 1u << ((lx & 1u) << 4)) == 0u;
           } else {
-            atomicAdd(grid_t + (size_t)cy * d.nx + cx, 1u);
+            global_add(grid_t + (size_t)cy * d.nx + cx, 1u);
           }
         } else {
           off = true;
@@ -238,13 +238,13 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
         const uint32_t ry = w / (uint32_t)half_w, rx = 2u * (w - ry * (uint32_t)half_w);
         uint32_t* g = grid_t + (size_t)(wd.y0 + ry) * d.nx + wd.x0 + rx;
         const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
-        if (lo) atomicAdd(g, lo);
-        if (hi) atomicAdd(g + 1, hi);
+        if (lo) global_add(g, lo);
+        if (hi) global_add(g + 1, hi);
       }
     }
     if (tid == 0) {
       const uint32_t v = sh.off[t & 1];
-      if (v && d.offgrid) atomicAdd(d.offgrid + (t - 1), v);
+      if (v && d.offgrid) global_add(d.offgrid + (t - 1), v);
       sh.off[t & 1] = 0u;
       // the list counter of step t-1 was read before this step's barrier and
       // is next appended to at step t+2, after the next barrier

@@ -108,6 +108,37 @@ def test_batched_equals_plain_and_single(orc, cap):
     Bp.close()
 
 
+@pytest.mark.parametrize("threads,ppt,blocks", [(256, 4, 7), (512, 4, 3), (512, 2, 5),
+                                                 (256, 1, 3), (512, 4, 0)])
+def test_tile_kinds_cover_every_particle(orc, cap, threads, ppt, blocks):
+    """The persistent launch cuts each human into big, half and quarter tiles
+    sized from the resident block count; whatever the cut, every particle is
+    rolled out once and the grids equal the per-human launches'."""
+    humans = small_scene()
+    tr = tracks_for(orc, humans, 4)
+    note(f"tile kinds: {threads} threads x {ppt}, grid {blocks or 'default'}")
+    shape = dict(block_threads=threads, particles_per_thread=ppt, grid_blocks=blocks)
+    A = make_server(cap, humans, **shape)
+    Bp = make_server(cap, humans, **shape)
+    for h in humans:
+        A.submit(request(cap, h, tr[h.hid][0]))
+        Bp.submit(request(cap, h, tr[h.hid][0]))
+    for c in range(2):
+        obs = {h.hid: tr[h.hid][c + 1] for h in humans}
+        A.step(obs)
+        Bp.step(obs, plain=True)
+        A.drain()
+        Bp.drain()
+        for h in humans:
+            a = snapshot(A, h.hid, c)
+            b = snapshot(Bp, h.hid, c)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (c, h.hid)
+            assert np.all(a[0].reshape(h.H, -1).sum(1) + a[2] == h.N)
+    A.close()
+    Bp.close()
+
+
 def test_full_size_many_humans_parity(orc, cap):
     sc = scenes.config3()
     humans = sc.humans
