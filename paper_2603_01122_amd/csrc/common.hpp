@@ -72,6 +72,11 @@ inline void continuous_step(int k, int K, double speed, double dt, float* sx, fl
 }
 
 // ---------------------------------------------------------------- device
+// Three-input exclusive or in one gfx950 V_BITOP3_B32 (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon et al., SC'11): per round two 32x32->64-bit products of
 // counter words 0 and 2, recombined with words 1 and 3 and the round key; the
 // key advances by the Weyl constants between rounds.
@@ -82,8 +87,8 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     // one v_mad_u64_u32 per product gives both halves
     const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
     const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c0 = n0;
     c1 = (uint32_t)p1;
     c2 = n2;

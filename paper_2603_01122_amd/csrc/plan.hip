@@ -127,12 +127,12 @@ __global__ void __launch_bounds__(256)
     const SlotDev& sd = sl[s];
     const int t = it - H->step_begin[s] + 1;
     const Window r = clear_region(sd, t);
-    global_ptr<uint32_t> p = as_global(sd.rd.counts) + (size_t)(t - 1) * sd.rd.nx * sd.rd.ny;
-    const int n = r.w * r.h;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int y = i / r.w, x = i - y * r.w;
-      p[(size_t)(r.y0 + y) * sd.rd.nx + r.x0 + x] = 0u;
-    }
+    global_ptr<uint32_t> p = as_global(sd.rd.counts) + (size_t)(t - 1) * sd.rd.nx * sd.rd.ny +
+                             (size_t)r.y0 * sd.rd.nx + r.x0;
+    // one wavefront per row of the region, lanes along the row (coalesced)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int y = wave; y < r.h; y += nw)
+      for (int x = lane; x < r.w; x += 64) p[(size_t)y * sd.rd.nx + x] = 0u;
     if (threadIdx.x == 0 && sd.rd.offgrid) as_global(sd.rd.offgrid)[t - 1] = 0u;
   }
 }
@@ -149,16 +149,16 @@ __global__ void __launch_bounds__(256)
     if (!sd.probs || sd.smooth_r > 0) continue;
     const int t = it - H->step_begin[s] + 1;
     const Window r = clear_region(sd, t);
-    const size_t plane = (size_t)(t - 1) * sd.rd.nx * sd.rd.ny;
-    const uint32_t* q = sd.rd.counts + plane;
-    float* p = sd.probs + plane;
+    const size_t origin = (size_t)(t - 1) * sd.rd.nx * sd.rd.ny + (size_t)r.y0 * sd.rd.nx + r.x0;
+    global_ptr<const uint32_t> q = as_global(static_cast<const uint32_t*>(sd.rd.counts)) + origin;
+    global_ptr<float> p = as_global(sd.probs) + origin;
     const float N = (float)sd.rd.N;
-    const int n = r.w * r.h;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int y = i / r.w, x = i - y * r.w;
-      const size_t c = (size_t)(r.y0 + y) * sd.rd.nx + r.x0 + x;
-      p[c] = (float)q[c] / N;
-    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int y = wave; y < r.h; y += nw)
+      for (int x = lane; x < r.w; x += 64) {
+        const size_t c = (size_t)y * sd.rd.nx + x;
+        p[c] = (float)q[c] / N;
+      }
   }
 }
 
