@@ -12,7 +12,12 @@ launch, normalisation).  Humans arrive and leave while cycles are in flight:
   ring entries of every per-cycle buffer, so cycle c+1 can start on the device
   while cycle c is still running; only the tiny belief updates are ordered;
 * latency -- a cycle's latency is the time from its release tick until the
-  host observes its completion event (polled, never a blocking wait).
+  host observes its completion event (polled, never a blocking wait);
+* host pauses -- Python's full garbage collections walk every tracked object
+  of the process (tens of milliseconds once torch is loaded) and land on
+  whichever cycle triggers them; the server freezes the heap that exists when
+  it starts (gc.freeze) so that later collections only walk what the loop
+  itself creates, and it keeps a bounded history of cycle records.
 
 Results are keyed by (human id, cycle, seed) alone, so a human's grids are the
 same whether it is served alone or in any mix.  Slot buffers are allocated
@@ -22,6 +27,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import gc
 import time
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -63,13 +69,16 @@ class Server:
                  particle_budget: Optional[int] = None, seed: int = 0, probs: bool = True,
                  tuning: Optional[dict] = None, max_smooth_radius: int = 0, speeds=None,
                  stationary: Optional[Tuple[float, int]] = None,
-                 goal_departure: Optional[float] = None, device="cuda"):
+                 goal_departure: Optional[float] = None, device="cuda",
+                 freeze_gc: bool = True, history: int = 1 << 16):
         """stationary = (eps, mask): a human whose newest observed step is shorter
         than eps metres is predicted with the allowed speeds `mask` only (Q = -inf
         for the others, Sec. IV-B) until it moves again.  goal_departure = r: a
         human that was within r metres of one of its goals and is now farther
         from all of them gets a uniform belief before the next update (Sec. IV-B).
-        The paper specifies neither detector; these are the simplest readings."""
+        The paper specifies neither detector; these are the simplest readings.
+        freeze_gc: gc.freeze() once the server is built (see the module notes).
+        history: how many of the latest CycleRecords `records` keeps."""
         tuning = tuning or {}
         self.plan = capred.Plan(K, speed, dt, n_slots, max_obs=1, ring=ring,
                                 max_smooth_radius=max_smooth_radius, speeds=speeds, **tuning)
@@ -101,8 +110,11 @@ class Server:
         self._dep: Optional[torch.cuda.Event] = None
         self._after_current_stream()
         self.cycle = 0
-        self.records: List[CycleRecord] = []
+        self.records: collections.deque = collections.deque(maxlen=max(1, history))
         self._pending: collections.deque = collections.deque()
+        if freeze_gc:
+            gc.collect()
+            gc.freeze()
 
     # ----------------------------------------------------------- admission
     def submit(self, r: HumanRequest):
@@ -241,7 +253,7 @@ def run_paced(server: Server, obs_fn, n_cycles: int, rate_hz: float = 125.0,
     event queries between ticks.  obs_fn(c) -> {hid: xy}.  Returns latencies (s)."""
     period = 1.0 / rate_hz
     t0 = time.perf_counter() + 2 * period
-    first = len(server.records)
+    recs = []
     for c in range(n_cycles):
         tick = t0 + c * period
         while True:
@@ -251,8 +263,8 @@ def run_paced(server: Server, obs_fn, n_cycles: int, rate_hz: float = 125.0,
                 break
             if tick - now > 200e-6:
                 time.sleep(min(tick - now - 150e-6, 1e-3))
-        server.step(obs_fn(c), release=tick)
+        recs.append(server.step(obs_fn(c), release=tick))
         if progress and (c + 1) % progress[0] == 0:
             progress[1](c + 1)
     server.drain()
-    return np.array([r.latency for r in server.records[first:]], np.float64)
+    return np.array([r.latency for r in recs], np.float64)
