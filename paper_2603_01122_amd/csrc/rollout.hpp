@@ -80,6 +80,8 @@ __device__ __forceinline__ uint32_t pick_word(const uint4& w, int s) {
 // LDS bytes of the histogram window of one block: two window buffers of
 // `cap` words (two 16-bit cell counters per word) and two lists of the words
 // first touched in a step (16-bit word indices, one per particle at most).
+// A step whose window needs more than `cap` words (and at most 2 cap) uses
+// both buffers as one and the first list.
 __host__ __device__ constexpr size_t window_lds_bytes(int cap, int particles_per_tile) {
   return (size_t)2 * cap * sizeof(uint32_t) + (size_t)2 * particles_per_tile * sizeof(uint16_t);
 }
@@ -88,7 +90,11 @@ __host__ __device__ constexpr size_t window_lds_bytes(int cap, int particles_per
 // win: window_lds_bytes(cap, P * blockDim.x) bytes of LDS, zero on entry and
 // on exit (cap <= 65536).  A step's window is flushed from the list of words
 // its particles touched first, so the flush costs one entry per occupied
-// word, whatever the window's area.
+// word, whatever the window's area.  Windows of up to cap words alternate
+// between the two buffers, so that a step's binning overlaps the previous
+// step's flush; windows of up to 2 cap words (and 2^16 words, the reach of a
+// list entry) take both buffers and wait at one more barrier for the previous
+// flush; larger windows bin with global atomics.
 //
 // MS (several speeds): draw_control over the S K controls; `ctl` is an LDS
 // array of CAP_MAX_U float4 that receives (fx, fy, s2) of every control, read
@@ -175,9 +181,13 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     // two 16-bit counters per LDS word (a tile never holds 65536 particles);
     // rows padded to an even number of cells
     const int half_w = (wd.w + 1) >> 1;
-    const bool lds_mode = half_w * wd.h <= cap;
-    uint32_t* buf = win + (t & 1) * cap;
-    uint16_t* list = lists + (t & 1) * list_cap;
+    const int words = half_w * wd.h;
+    const bool single = words > cap && words <= 2 * cap && words <= 65536;
+    const bool lds_mode = words <= cap || single;
+    uint32_t* buf = single ? win : win + (t & 1) * cap;
+    uint16_t* list = single ? lists : lists + (t & 1) * list_cap;
+    // both buffers: the previous step's flush (of either buffer) must be over
+    if (single) __syncthreads();
     uint32_t* grid_t = d.counts + (size_t)(t - 1) * plane;
     bool off_any = false;
 #pragma unroll

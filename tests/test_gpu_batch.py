@@ -139,6 +139,33 @@ def test_tile_kinds_cover_every_particle(orc, cap, threads, ppt, blocks):
     Bp.close()
 
 
+@pytest.mark.parametrize("lds", [2048, 4096])
+def test_window_modes_match_single_human(orc, cap, lds):
+    """A small LDS budget drives late steps through the three binning modes
+    (two alternating window buffers, both buffers as one, global atomics);
+    the counts are exact integers, so they equal the single-human launch's
+    (default budget: every step in the first mode)."""
+    humans = small_scene(n=3, H=60)
+    tr = tracks_for(orc, humans, 3)
+    note(f"window modes: lds {lds} B, H=60")
+    srv = make_server(cap, humans, block_threads=256, particles_per_thread=2, lds_bytes=lds)
+    for h in humans:
+        srv.submit(request(cap, h, tr[h.hid][0]))
+    for c in range(2):
+        srv.step({h.hid: tr[h.hid][c + 1] for h in humans})
+        srv.drain()
+        for h in humans:
+            counts, probs, off, post = snapshot(srv, h.hid, c)
+            out = cap.predict_occupancy(cap.model_of(h), h.grid,
+                                        tuple(tr[h.hid][c + 1].astype(float)),
+                                        torch.tensor(post, device="cuda"), h.N, h.H, seed=0,
+                                        human_id=h.hid, cycle=c)
+            torch.cuda.synchronize()
+            assert np.array_equal(out["counts"].cpu().numpy(), counts), (c, h.hid)
+            assert np.array_equal(out["offgrid"].cpu().numpy(), off), (c, h.hid)
+    srv.close()
+
+
 def test_full_size_many_humans_parity(orc, cap):
     sc = scenes.config3()
     humans = sc.humans
