@@ -314,7 +314,11 @@ cap_status cap_plan_run(cap_plan* plan, uint64_t seed, uint32_t cycle, void* str
 cap_status cap_plan_replay_rollout(cap_plan* plan, void* stream, void* ev_start, void* ev_end);
 /* Block the host until the last run has completed on the device. */
 cap_status cap_plan_sync(cap_plan* plan);
-/* Totals over the active slots: particles, particle-steps, rollout tiles. */
+/* Totals over the active slots: particles, particle-steps, and tiles of
+ * particles_per_thread * block_threads particles (the per-human launches'
+ * tiles; the persistent launch cuts the same particles into tiles of that
+ * size, half of it and a quarter of it, sized per cycle to the resident
+ * blocks). */
 cap_status cap_plan_stats(const cap_plan* plan, int64_t* particles, int64_t* particle_steps,
                           int32_t* tiles);
 /* Effective tuning of the plan (after defaults are resolved). */
