@@ -14,8 +14,10 @@ about 16 x 3 KB, crosses PCIe, as it would in serving).
 Reported: particle-steps/s of back-to-back batched cycles (`value`); the
 same for the plain per-human sequential launches (the paper's multi-human
 procedure, Sec. IV-B) and their ratio; p50/p99 latency of a 125 Hz paced
-loop; the rollout kernel's roofline (live HIP-event timing); and the FP64
-oracle timed on the host cores on one full cycle.
+loop; the rollout kernel's roofline (live HIP-event timing); the 64-human
+scene; the consumers (union of the grids, one MPPI step); the differentiable
+log-likelihood and its adjoint on 1024 tracks; one Tab. 1-shaped prediction;
+and the FP64 oracle timed on the host cores over whole cycles (at least 10 s).
 """
 from __future__ import annotations
 
@@ -207,6 +209,43 @@ def mppi_timing(capred, torch, np, srv, humans, cycle, reps=20):
     return {"union_ms": round(float(np.median(tu)), 4),
             "union_GBps": round(cells * 4 * (len(probs) + 1) / (np.median(tu) * 1e-3) / 1e9, 1),
             "mppi_ms": round(float(np.median(tm)), 4), "samples": N, "horizon": T}
+
+
+def loglik_timing(capred, torch, np, scenes, reps=20):
+    """The differentiation workload: 1024 tracks of 200 transitions (K = 32,
+    dt = 0.05 s, per-track beta and one of 8 goals, simulated on the GPU), the
+    batched log-likelihood over 8 goals x 9 beta and its adjoint with respect
+    to the goals and log beta (median of `reps` calls each)."""
+    ts = scenes.config4()
+    n = ts.starts.shape[0]
+    start = torch.tensor(ts.starts, dtype=torch.float64, device="cuda")
+    beta = torch.tensor(ts.true_beta, dtype=torch.float32, device="cuda")
+    goal = torch.tensor(ts.goals[ts.true_goal], dtype=torch.float32, device="cuda")
+    _, pos = capred.simulate_tracks(ts.K, ts.speed, ts.dt, ts.frame, start, beta, goal, ts.T,
+                                    seed=0, stream_id=4)
+    tracks = pos.contiguous()
+    lengths = torch.full((n,), ts.T, dtype=torch.int32, device="cuda")
+    goals = torch.tensor(ts.goals, device="cuda")
+    log_beta = torch.tensor(np.log(ts.beta_grid).astype(np.float32), device="cuda")
+    dLL = torch.ones((n, log_beta.numel(), goals.shape[0]), dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tf, tb = [], []
+    for k in range(reps + 2):
+        ev[0].record()
+        capred.loglik(ts.K, ts.speed, ts.dt, tracks, lengths, goals, log_beta)
+        ev[1].record()
+        capred.loglik_backward(ts.K, ts.speed, ts.dt, tracks, lengths, goals, log_beta, dLL)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if k >= 2:
+            tf.append(ev[0].elapsed_time(ev[1]))
+            tb.append(ev[1].elapsed_time(ev[2]))
+    terms = n * ts.T * goals.shape[0] * log_beta.numel()
+    fwd, bwd = float(np.median(tf)), float(np.median(tb))
+    return {"tracks": n, "steps": ts.T, "goals": int(goals.shape[0]), "beta": int(log_beta.numel()),
+            "K": ts.K, "forward_ms": round(fwd, 4), "backward_ms": round(bwd, 4),
+            "policy_terms_per_s_forward": float(f"{terms / (fwd * 1e-3):.4e}"),
+            "policy_terms_per_s_backward": float(f"{terms / (bwd * 1e-3):.4e}")}
 
 
 def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
@@ -442,6 +481,9 @@ def main():
         c += args.paced_cycles
     srv.drain()
     mppi = mppi_timing(capred, torch, np, srv, humans, c - 1)
+    diff = loglik_timing(capred, torch, np, scenes)
+    log(f"log-likelihood, 1024 tracks x 200 steps x 8 goals x 9 beta: forward "
+        f"{diff['forward_ms']} ms, backward {diff['backward_ms']} ms")
     log(f"union of 16 grids {mppi['union_ms']} ms ({mppi['union_GBps']} GB/s), "
         f"MPPI step {mppi['mppi_ms']} ms")
     srv.close()
@@ -515,6 +557,7 @@ def main():
         "cpu_baseline": cpu,
         "largest_scene": largest,
         "consumer": mppi,
+        "differentiation": diff,
         "tab1_shaped": tab1,
         "context": "paper: ~125 Hz for one human, n=8192, T=10, |U|=96 on an RTX 2080 Ti "
                    "(Tab. 1, JAX/XLA), about 1.0e7 particle-steps/s; different workload and hardware",

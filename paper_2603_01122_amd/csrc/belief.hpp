@@ -64,16 +64,18 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
   const float D = sqrtf(D2);
   const float ax2 = ax + ax, ay2 = ay + ay;
   float dl[NMAX];
+  float dmin = INFINITY;
   for (int k = 0; k < U; ++k) {
     const float corr = fmaf(2.f * ax_lo, m.sx[k], fmaf(2.f * ay_lo, m.sy[k], m.s2[k]));
     const float n = fmaf(ax2, m.sx[k], fmaf(ay2, m.sy[k], corr));
     const float d = sqrtf(fmaxf(D2 + n, 0.f));
     dl[k] = n / (d + D);
+    dmin = fminf(dmin, dl[k]);
   }
   for (int b = 0; b < B; ++b) {
     const float nbt = -beta[b];
-    float mx = -INFINITY;
-    for (int k = 0; k < U; ++k) mx = fmaxf(mx, nbt * dl[k]);
+    // max_k (nbt dl_k) for nbt <= 0: the rounded product is monotone in dl_k
+    const float mx = nbt * dmin;
     float s = 0.f;
     for (int k = 0; k < U; ++k) s += expf(nbt * dl[k] - mx);
     out[b] = (nbt * dl[ks] - mx) - logf(s);

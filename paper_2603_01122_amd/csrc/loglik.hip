@@ -60,15 +60,19 @@ __global__ void __launch_bounds__(kLLThreads) loglik_kernel(const LLArgs a, doub
 //   d ell/d log beta = -beta (Delta_{k*} - E_p[Delta]),
 // with yhat_k = (a + s_k)/d_k and, to avoid cancellation between unit vectors,
 //   yhat_k - yhat_* = a (Delta_* - Delta_k)/(d_k d_*) + s_k/d_k - s_*/d_*.
+// KT > 0: the model has KT headings (loops over headings fully unrolled, so
+// the per-heading arrays stay in registers); KT == 0: any K.
+template <int KT>
 __global__ void __launch_bounds__(kLLThreads)
     loglik_backward_kernel(const LLArgs a, const double* __restrict__ dLL,
                            double* __restrict__ ws_g, double* __restrict__ ws_b) {
+  constexpr int KM = KT > 0 ? KT : CAP_MAX_K;
   const int lane = threadIdx.x & 63;
   const int item = blockIdx.x * (kLLThreads / 64) + (threadIdx.x >> 6);
   if (item >= a.N * a.G) return;
   const int n = item / a.G, g = item - n * a.G;
   const int len = a.lengths[n];
-  const int K = a.m.K, B = a.B;
+  const int K = KT > 0 ? KT : a.m.K, B = a.B;
   const float* z = a.tracks + (size_t)n * (a.Tmax + 1) * 2;
   const float gx = a.goals[2 * g], gy = a.goals[2 * g + 1];
   float beta[CAP_MAX_B], w[CAP_MAX_B];
@@ -76,7 +80,7 @@ __global__ void __launch_bounds__(kLLThreads)
   for (int b = 0; b < B; ++b) w[b] = (float)dLL[((size_t)n * B + b) * a.G + g];
   double agx = 0.0, agy = 0.0, ab[CAP_MAX_B];
   for (int b = 0; b < B; ++b) ab[b] = 0.0;
-  float dl[CAP_MAX_K], dk[CAP_MAX_K];
+  float dl[KM], dk[KM];
   for (int t = lane; t < len; t += 64) {
     const float zx = z[2 * t], zy = z[2 * t + 1];
     const int ks = recover_control(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
@@ -87,46 +91,94 @@ __global__ void __launch_bounds__(kLLThreads)
     const float ay_lo = (zy - (ay - by)) + (-gy - by);
     const float D2 = fmaf(ax, ax, ay * ay);
     const float D = sqrtf(D2);
-    for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      if (KT == 0 && k >= K) break;
       const float corr = fmaf(2.f * ax_lo, a.m.sx[k], fmaf(2.f * ay_lo, a.m.sy[k], a.m.s2[k]));
       const float nk = fmaf(ax + ax, a.m.sx[k], fmaf(ay + ay, a.m.sy[k], corr));
       dk[k] = sqrtf(fmaxf(D2 + nk, 0.f));
       dl[k] = nk / (dk[k] + D);
     }
-    const float ds = dk[ks];
-    for (int b = 0; b < B; ++b) {
-      const float nbt = -beta[b];
-      float mx = -INFINITY;
-      for (int k = 0; k < K; ++k) mx = fmaxf(mx, nbt * dl[k]);
-      float s = 0.f, ex = 0.f, ey = 0.f, ed = 0.f;
-      for (int k = 0; k < K; ++k) {
-        const float p = expf(nbt * dl[k] - mx);
-        s += p;
-        // yhat_k - yhat_*  (yhat := 0 where the distance is 0)
-        float ux, uy;
+    if constexpr (KT > 0) {
+      const float ds = dk[ks], dls = dl[ks], sxs = a.m.sx[ks], sys = a.m.sy[ks];
+      // yhat_k - yhat_* once per heading (independent of beta; yhat := 0 where
+      // the distance is 0), and max_k (-beta dl_k) = -beta min_k dl_k exactly
+      // (the rounded product is monotone in dl_k)
+      float ux[KM], uy[KM];
+      float dmin = INFINITY;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
         if (dk[k] > 0.f && ds > 0.f) {
-          const float v = (dl[ks] - dl[k]) / (dk[k] * ds);
-          ux = fmaf(ax, v, a.m.sx[k] / dk[k] - a.m.sx[ks] / ds);
-          uy = fmaf(ay, v, a.m.sy[k] / dk[k] - a.m.sy[ks] / ds);
+          const float v = (dls - dl[k]) / (dk[k] * ds);
+          ux[k] = fmaf(ax, v, a.m.sx[k] / dk[k] - sxs / ds);
+          uy[k] = fmaf(ay, v, a.m.sy[k] / dk[k] - sys / ds);
         } else if (dk[k] > 0.f) {
-          ux = (ax + a.m.sx[k]) / dk[k];
-          uy = (ay + a.m.sy[k]) / dk[k];
+          ux[k] = (ax + a.m.sx[k]) / dk[k];
+          uy[k] = (ay + a.m.sy[k]) / dk[k];
         } else if (ds > 0.f) {
-          ux = -(ax + a.m.sx[ks]) / ds;
-          uy = -(ay + a.m.sy[ks]) / ds;
+          ux[k] = -(ax + sxs) / ds;
+          uy[k] = -(ay + sys) / ds;
         } else {
-          ux = 0.f;
-          uy = 0.f;
+          ux[k] = 0.f;
+          uy[k] = 0.f;
         }
-        ex = fmaf(p, ux, ex);
-        ey = fmaf(p, uy, ey);
-        ed = fmaf(p, dl[k] - dl[ks], ed);
+        dmin = fminf(dmin, dl[k]);
       }
-      const float inv = 1.f / s;
-      // E[yhat] - yhat_* = ex/s ; E[Delta] - Delta_* = ed/s
-      agx += (double)(w[b] * (nbt * (ex * inv)));
-      agy += (double)(w[b] * (nbt * (ey * inv)));
-      ab[b] += (double)(w[b] * (beta[b] * (ed * inv)));
+      for (int b = 0; b < B; ++b) {
+        const float nbt = -beta[b];
+        const float mx = nbt * dmin;
+        float s = 0.f, ex = 0.f, ey = 0.f, ed = 0.f;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const float p = expf(nbt * dl[k] - mx);
+          s += p;
+          ex = fmaf(p, ux[k], ex);
+          ey = fmaf(p, uy[k], ey);
+          ed = fmaf(p, dl[k] - dls, ed);
+        }
+        const float inv = 1.f / s;
+        // E[yhat] - yhat_* = ex/s ; E[Delta] - Delta_* = ed/s
+        agx += (double)(w[b] * (nbt * (ex * inv)));
+        agy += (double)(w[b] * (nbt * (ey * inv)));
+        ab[b] += (double)(w[b] * (beta[b] * (ed * inv)));
+      }
+    } else {
+      // any K: per (beta, heading), without per-heading arrays beyond dl and dk
+      const float ds = dk[ks];
+      for (int b = 0; b < B; ++b) {
+        const float nbt = -beta[b];
+        float mx = -INFINITY;
+        for (int k = 0; k < K; ++k) mx = fmaxf(mx, nbt * dl[k]);
+        float s = 0.f, ex = 0.f, ey = 0.f, ed = 0.f;
+        for (int k = 0; k < K; ++k) {
+          const float p = expf(nbt * dl[k] - mx);
+          s += p;
+          // yhat_k - yhat_*  (yhat := 0 where the distance is 0)
+          float ux, uy;
+          if (dk[k] > 0.f && ds > 0.f) {
+            const float v = (dl[ks] - dl[k]) / (dk[k] * ds);
+            ux = fmaf(ax, v, a.m.sx[k] / dk[k] - a.m.sx[ks] / ds);
+            uy = fmaf(ay, v, a.m.sy[k] / dk[k] - a.m.sy[ks] / ds);
+          } else if (dk[k] > 0.f) {
+            ux = (ax + a.m.sx[k]) / dk[k];
+            uy = (ay + a.m.sy[k]) / dk[k];
+          } else if (ds > 0.f) {
+            ux = -(ax + a.m.sx[ks]) / ds;
+            uy = -(ay + a.m.sy[ks]) / ds;
+          } else {
+            ux = 0.f;
+            uy = 0.f;
+          }
+          ex = fmaf(p, ux, ex);
+          ey = fmaf(p, uy, ey);
+          ed = fmaf(p, dl[k] - dl[ks], ed);
+        }
+        const float inv = 1.f / s;
+        // E[yhat] - yhat_* = ex/s ; E[Delta] - Delta_* = ed/s
+        agx += (double)(w[b] * (nbt * (ex * inv)));
+        agy += (double)(w[b] * (nbt * (ey * inv)));
+        ab[b] += (double)(w[b] * (beta[b] * (ed * inv)));
+      }
     }
   }
   const double sgx = wave_sum(agx), sgy = wave_sum(agy);
@@ -242,8 +294,14 @@ extern "C" cap_status cap_loglik_backward(int32_t K, double speed, double dt,
   double* ws_b = ws_g + (size_t)N * G * 2;
   if (N > 0) {
     const int items = N * G, per_block = kLLThreads / 64;
-    hipLaunchKernelGGL(loglik_backward_kernel, dim3((items + per_block - 1) / per_block),
-                       dim3(kLLThreads), 0, s, a, dLL_dev, ws_g, ws_b);
+    const dim3 grid((items + per_block - 1) / per_block), block(kLLThreads);
+    switch (a.m.K) {
+      case 4: hipLaunchKernelGGL(loglik_backward_kernel<4>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
+      case 8: hipLaunchKernelGGL(loglik_backward_kernel<8>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
+      case 16: hipLaunchKernelGGL(loglik_backward_kernel<16>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
+      case 32: hipLaunchKernelGGL(loglik_backward_kernel<32>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
+      default: hipLaunchKernelGGL(loglik_backward_kernel<0>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
+    }
     CAP_HIP(hipGetLastError());
   }
   const int outs = 2 * G + (per_track_beta ? N * B : B);
