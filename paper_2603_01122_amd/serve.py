@@ -249,20 +249,22 @@ class Server:
 
 def run_paced(server: Server, obs_fn, n_cycles: int, rate_hz: float = 125.0,
               progress=None) -> np.ndarray:
-    """Fixed-rate loop: cycle c is released at t0 + c/rate; the host spins on
-    event queries between ticks.  obs_fn(c) -> {hid: xy}.  Returns latencies (s)."""
+    """Fixed-rate loop: cycle c is released at t0 + c/rate; between ticks the
+    host polls the completion events, every ~50 us while a cycle is in flight
+    (so that a completion is seen within about that) and every millisecond
+    otherwise.  obs_fn(c) -> {hid: xy}.  Returns latencies (s)."""
     period = 1.0 / rate_hz
     t0 = time.perf_counter() + 2 * period
     recs = []
     for c in range(n_cycles):
         tick = t0 + c * period
         while True:
-            server.poll()
+            pending = server.poll()
             now = time.perf_counter()
             if now >= tick:
                 break
             if tick - now > 200e-6:
-                time.sleep(min(tick - now - 150e-6, 1e-3))
+                time.sleep(min(tick - now - 150e-6, 50e-6 if pending else 1e-3))
         recs.append(server.step(obs_fn(c), release=tick))
         if progress and (c + 1) % progress[0] == 0:
             progress[1](c + 1)
