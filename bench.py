@@ -56,10 +56,31 @@ def algorithmic_ops(K: int, r: dict) -> float:
     r[kind] slots (the mixed probe -- one exp2 with four full-rate ops costs
     about five slots, not 3 + 4 -- shows the overlap), so the time is
     max(issue slots, transcendental pipe)."""
+    issue, pipe = algorithmic_slots(K, r)
+    return max(issue, pipe)
+
+
+def algorithmic_slots(K: int, r: dict):
+    """(issue slots, transcendental-pipe slots) per particle-step; see algorithmic_ops."""
     trans = K * 3 + 1
     issue = K * 6 + 2 * math.log2(K) + 22 + 10 + trans + 5 * r["mul64"]
     pipe = K * (r["sqrt"] + r["rcp"] + r["exp2"]) + r["sqrt"]
-    return max(issue, pipe)
+    return issue, pipe
+
+
+def resource_use(rates, K, psteps, seconds, traffic):
+    """Each resource of the rollout against its peak over one launch: VALU
+    issue and the transcendental pipe (algorithmic slots, see algorithmic_ops),
+    LDS atomics (one add per particle-step into the step's window; the probe's
+    scattered-address LDS atomic rate is the peak) and HBM bytes (the profiled
+    traffic, if current; 8 TB/s)."""
+    issue, pipe = algorithmic_slots(K, rates)
+    out = {"valu_issue": round(issue * psteps / seconds / PEAK_LANE_OPS, 4),
+           "transcendental_pipe": round(pipe * psteps / seconds / PEAK_LANE_OPS, 4),
+           "lds_atomic": round(psteps / seconds / rates["lds_atomic_lane_ops_per_s"], 4),
+           "lds_atomic_peak_lane_ops_per_s": float(f"{rates['lds_atomic_lane_ops_per_s']:.4e}"),
+           "hbm": None if traffic is None else round(traffic / seconds / 8e12, 5)}
+    return out
 
 
 def measure_rates(capred, torch) -> dict:
@@ -70,7 +91,7 @@ def measure_rates(capred, torch) -> dict:
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     out = {}
     iters = 4096
-    for kind in ("fma", "exp2", "sqrt", "rcp", "mul64", "mix"):
+    for kind in ("fma", "exp2", "sqrt", "rcp", "mul64", "mix", "lds_atomic"):
         capred.probe(kind, 64, blocks, sink)
         e0.record()
         capred.probe(kind, iters, blocks, sink)
@@ -81,6 +102,7 @@ def measure_rates(capred, torch) -> dict:
         out[kind] = ops / (ms * 1e-3)
     rates = {k: out["fma"] / v for k, v in out.items()}
     rates["fma_lane_ops_per_s"] = out["fma"]
+    rates["lds_atomic_lane_ops_per_s"] = out["lds_atomic"]
     return rates
 
 
@@ -295,6 +317,7 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
     psteps = sc.particle_steps
     W = algorithmic_ops(humans[0].K, rates)
     achieved = W * psteps / roll
+    resources = resource_use(rates, humans[0].K, psteps, roll, None)
     return {"workload": "64 humans x 2^20 particles, 6 goals, 9 beta, K=32, v=1.2 m/s, "
                         "dt=0.01 s, H=200, 512x512 grids at 0.02 m",
             "particle_steps_per_cycle": psteps, "cycles": cycles,
@@ -307,7 +330,8 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
                          "ops_per_particle_step": round(W, 2),
                          "achieved": round(achieved / 1e12, 3),
                          "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
-                         "frac": round(achieved / PEAK_LANE_OPS, 4)}}
+                         "frac": round(achieved / PEAK_LANE_OPS, 4),
+                         "resources": resources}}
 
 
 def tab1_latency(capred, torch, np, calls=50):
@@ -396,7 +420,7 @@ def main():
     tracks = simulate(capred, torch, np, humans, T)
 
     rates = measure_rates(capred, torch)
-    log(f"probe rates (cost relative to FMA): { {k: round(v, 3) for k, v in rates.items() if k != 'fma_lane_ops_per_s'} }")
+    log(f"probe rates (cost relative to FMA): { {k: round(v, 3) for k, v in rates.items() if not k.endswith('_per_s')} }")
 
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
@@ -456,9 +480,10 @@ def main():
     roll = float(np.mean(durs))
     W = algorithmic_ops(humans[0].K, rates)
     achieved = W * psteps / roll
+    traffic = profiled_traffic(best)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
-                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": profiled_traffic(best),
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": traffic,
                 # the same work per back-to-back cycle (consecutive rollouts overlap
                 # their tails on the two streams): a serving-throughput view
                 "cycle_frac": round(W * psteps / sec_per_cycle / PEAK_LANE_OPS, 4),
@@ -466,8 +491,9 @@ def main():
                 "ops_per_particle_step": round(W, 2),
                 "particle_steps_per_launch": psteps,
                 "rates_vs_fma": {k: round(v, 3) for k, v in rates.items()
-                                 if k != "fma_lane_ops_per_s"},
-                "fma_lane_ops_per_s": float(f"{rates['fma_lane_ops_per_s']:.4e}")}
+                                 if not k.endswith("_per_s")},
+                "fma_lane_ops_per_s": float(f"{rates['fma_lane_ops_per_s']:.4e}"),
+                "resources": resource_use(rates, humans[0].K, psteps, roll, traffic)}
     log(f"rollout kernel {roll * 1e3:.3f} ms, {W:.1f} ops/particle-step, frac {achieved / PEAK_LANE_OPS:.3f}")
 
     # ---------------------------------------------------------- paced 125 Hz serving
