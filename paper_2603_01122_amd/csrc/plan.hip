@@ -453,8 +453,8 @@ static void destroy_plan(cap_plan* p) {
 // kind-k tile holds P >> k units.  With R resident blocks on C CUs and U units
 // in all, whole rounds of big tiles (one per block) take the first
 // P R floor(U / (P R)) units.  The remainder Ur is spread over the CUs, one
-// tile per CU at a time, largest first: one big tile per CU while Ur exceeds
-// 4 C; then, for what is left, quarters (Ur <= C), halves and quarters
+// tile per CU at a time, largest first: one big tile per CU for as long as Ur
+// exceeds 4 C; then, for what is left, quarters (Ur <= C), halves and quarters
 // (Ur <= 2 C) or big tiles and halves (Ur <= 4 C), with as many tiles as CUs
 // (or fewer).  A tile that ends up alone on its CU runs faster than one of a
 // pair, so the last tiles even out the CUs rather than the blocks.  Each
@@ -469,7 +469,7 @@ static void split_tiles(const int32_t* units, int n, int P, int R, int C,
   C = std::max(1, std::min(C, R));
   if (P >= 4) {
     int64_t Ur = U % ((int64_t)P * R);
-    if (Ur > 4 * (int64_t)C) Ur -= 4 * (int64_t)C;
+    while (Ur > 4 * (int64_t)C) Ur -= 4 * (int64_t)C;
     if (Ur == 0) {
     } else if (Ur <= C) {
       t_quarter = Ur;
@@ -484,7 +484,7 @@ static void split_tiles(const int32_t* units, int n, int P, int R, int C,
   } else if (P == 2) {
     // kind 1 is the one-unit tile
     int64_t Ur = U % (2 * (int64_t)R);
-    if (Ur > 2 * (int64_t)C) Ur -= 2 * (int64_t)C;
+    while (Ur > 2 * (int64_t)C) Ur -= 2 * (int64_t)C;
     if (Ur <= C) t_half = Ur;
     else t_half = 2 * (int64_t)C - Ur;
   }
