@@ -323,6 +323,17 @@ cap_status cap_plan_stats(const cap_plan* plan, int64_t* particles, int64_t* par
                           int32_t* tiles);
 /* Effective tuning of the plan (after defaults are resolved). */
 cap_status cap_plan_tuning(const cap_plan* plan, cap_plan_config* out);
+/* The cut of a cycle's particles into the persistent launch's tiles (host
+ * only, no device work; the plan applies it every cycle): units[i] =
+ * ceil(N_i / block_threads) for the n active humans (HOST array, each >= 0),
+ * particles_per_thread P in {1, 2, 4}, resident_blocks R >= 1 on cus C >= 1
+ * compute units.  Writes counts[i][k] (HOST array [n][3]): the number of tiles
+ * of human i holding P >> k units (k = 0, 1, 2; only sizes >= 1 occur), with
+ * sum_k counts[i][k] (P >> k) = units[i].  Whole rounds of big tiles (one per
+ * block) come first; the remainder is spread over the CUs one tile per CU at
+ * a time, largest first.  CAP_E_INVALID on bad sizes or NULL pointers. */
+cap_status cap_plan_tile_split(const int32_t* units, int32_t n, int32_t particles_per_thread,
+                               int32_t resident_blocks, int32_t cus, int32_t* counts);
 
 /* Plain per-human reference of one serving cycle (the paper's sequential
  * multi-human procedure, Sec. IV-B): for each active slot in turn, belief

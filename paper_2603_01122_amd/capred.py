@@ -127,10 +127,11 @@ if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_stats", _i32, _vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32))
     _sig("cap_plan_tuning", _i32, _vp, C.POINTER(cap_plan_config))
     _sig("cap_plan_replay_rollout", _i32, _vp, _vp, _vp, _vp)
+    _sig("cap_plan_tile_split", _i32, C.POINTER(_i32), _i32, _i32, _i32, _i32, C.POINTER(_i32))
     EXPORTED += ["cap_plan_replay_rollout", "cap_plan_create", "cap_plan_destroy", "cap_plan_set_slot",
                  "cap_plan_clear_slot", "cap_plan_stage_obs", "cap_plan_run",
                  "cap_plan_run_plain", "cap_plan_sync", "cap_plan_stats", "cap_plan_tuning",
-                 "cap_plan_set_speed_mask", "cap_plan_reset_belief"]
+                 "cap_plan_set_speed_mask", "cap_plan_reset_belief", "cap_plan_tile_split"]
 
 
 def _check(rc: int, what: str):
@@ -466,6 +467,18 @@ class SlotBuffers:
             torch.empty((ring, H), dtype=torch.int32, device=device),
             torch.empty((model.G, model.B), dtype=torch.float64, device=device),
             torch.empty((ring, model.G, model.B), dtype=torch.float64, device=device))
+
+
+def tile_split(units, particles_per_thread: int, resident_blocks: int, cus: int) -> np.ndarray:
+    """Tiles of the persistent launch per human: counts [n, 3] of tiles holding
+    P, P/2 and P/4 units of block_threads particles (host computation)."""
+    u = np.ascontiguousarray(units, np.int32).reshape(-1)
+    out = np.zeros((u.size, 3), np.int32)
+    _check(_lib.cap_plan_tile_split(u.ctypes.data_as(C.POINTER(C.c_int32)), u.size,
+                                    particles_per_thread, resident_blocks, cus,
+                                    out.ctypes.data_as(C.POINTER(C.c_int32))),
+           "cap_plan_tile_split")
+    return out
 
 
 class Plan:

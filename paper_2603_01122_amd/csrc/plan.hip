@@ -957,6 +957,21 @@ extern "C" cap_status cap_plan_stats(const cap_plan* p, int64_t* particles,
   return CAP_OK;
 }
 
+extern "C" cap_status cap_plan_tile_split(const int32_t* units, int32_t n,
+                                          int32_t particles_per_thread, int32_t resident_blocks,
+                                          int32_t cus, int32_t* counts) {
+  if (n < 0 || n > CAP_MAX_SLOTS) return fail(CAP_E_INVALID, "n must be in [0, CAP_MAX_SLOTS]");
+  if (particles_per_thread != 1 && particles_per_thread != 2 && particles_per_thread != 4)
+    return fail(CAP_E_INVALID, "particles_per_thread must be 1, 2 or 4");
+  if (resident_blocks < 1 || cus < 1) return fail(CAP_E_INVALID, "resident_blocks and cus >= 1");
+  if (n > 0 && (!units || !counts)) return fail(CAP_E_INVALID, "units or counts is NULL");
+  for (int i = 0; i < n; ++i)
+    if (units[i] < 0) return fail(CAP_E_INVALID, "units must be >= 0");
+  split_tiles(units, n, particles_per_thread, resident_blocks, cus,
+              reinterpret_cast<int32_t(*)[kTileKinds]>(counts));
+  return CAP_OK;
+}
+
 extern "C" cap_status cap_plan_tuning(const cap_plan* p, cap_plan_config* out) {
   if (!p || !out) return fail(CAP_E_INVALID, "plan or out is NULL");
   *out = p->cfg;
