@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(kLLThreads)
     }
     if constexpr (KT > 0) {
       const float ds = dk[ks], dls = dl[ks], sxs = a.m.sx[ks], sys = a.m.sy[ks];
+      const float sxs_ds = ds > 0.f ? sxs / ds : 0.f, sys_ds = ds > 0.f ? sys / ds : 0.f;
       // yhat_k - yhat_* once per heading (independent of beta; yhat := 0 where
       // the distance is 0), and max_k (-beta dl_k) = -beta min_k dl_k exactly
       // (the rounded product is monotone in dl_k)
@@ -110,8 +111,8 @@ __global__ void __launch_bounds__(kLLThreads)
       for (int k = 0; k < KM; ++k) {
         if (dk[k] > 0.f && ds > 0.f) {
           const float v = (dls - dl[k]) / (dk[k] * ds);
-          ux[k] = fmaf(ax, v, a.m.sx[k] / dk[k] - sxs / ds);
-          uy[k] = fmaf(ay, v, a.m.sy[k] / dk[k] - sys / ds);
+          ux[k] = fmaf(ax, v, a.m.sx[k] / dk[k] - sxs_ds);
+          uy[k] = fmaf(ay, v, a.m.sy[k] / dk[k] - sys_ds);
         } else if (dk[k] > 0.f) {
           ux[k] = (ax + a.m.sx[k]) / dk[k];
           uy[k] = (ay + a.m.sy[k]) / dk[k];
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(kLLThreads)
         float s = 0.f, ex = 0.f, ey = 0.f, ed = 0.f;
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
-            const float p = expf(nbt * dl[k] - mx);
+            const float p = exp_nonpos(nbt * dl[k] - mx);
           s += p;
           ex = fmaf(p, ux[k], ex);
           ey = fmaf(p, uy[k], ey);
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(kLLThreads)
         for (int k = 0; k < K; ++k) mx = fmaxf(mx, nbt * dl[k]);
         float s = 0.f, ex = 0.f, ey = 0.f, ed = 0.f;
         for (int k = 0; k < K; ++k) {
-          const float p = expf(nbt * dl[k] - mx);
+          const float p = exp_nonpos(nbt * dl[k] - mx);
           s += p;
           // yhat_k - yhat_*  (yhat := 0 where the distance is 0)
           float ux, uy;
