@@ -87,6 +87,40 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
   }
 }
 
+// policy_terms for one beta without a per-control array (so that large
+// control sets stay out of scratch memory): the smallest Delta in a first pass
+// over the controls, the exponential sum in a second pass that recomputes
+// each Delta with the same arithmetic (bit-identical to policy_terms).
+__device__ __forceinline__ float policy_term_one(const BeliefModel& m, float zx, float zy, int ks,
+                                                 float gx, float gy, float beta) {
+  if (ks < 0) return 0.f;
+  const int U = m.U;
+  const float ax = zx - gx, bx = ax - zx;
+  const float ax_lo = (zx - (ax - bx)) + (-gx - bx);
+  const float ay = zy - gy, by = ay - zy;
+  const float ay_lo = (zy - (ay - by)) + (-gy - by);
+  const float D2 = fmaf(ax, ax, ay * ay);
+  const float D = sqrtf(D2);
+  const float ax2 = ax + ax, ay2 = ay + ay;
+  auto delta = [&](int k) {
+    const float corr = fmaf(2.f * ax_lo, m.sx[k], fmaf(2.f * ay_lo, m.sy[k], m.s2[k]));
+    const float n = fmaf(ax2, m.sx[k], fmaf(ay2, m.sy[k], corr));
+    const float d = sqrtf(fmaxf(D2 + n, 0.f));
+    return n / (d + D);
+  };
+  float dmin = INFINITY, dks = 0.f;
+  for (int k = 0; k < U; ++k) {
+    const float dl = delta(k);
+    dmin = fminf(dmin, dl);
+    if (k == ks) dks = dl;
+  }
+  const float nbt = -beta;
+  const float mx = nbt * dmin;
+  float s = 0.f;
+  for (int k = 0; k < U; ++k) s += exp_nonpos(nbt * delta(k) - mx);
+  return (nbt * dks - mx) - logf(s);
+}
+
 __device__ __forceinline__ double block_reduce(double v, bool is_max, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
@@ -121,9 +155,7 @@ __device__ void belief_update_block(const BeliefModel& m, const float* __restric
       const int tl = item / J, j = item - tl * J, g = j / B, b = j - g * B, t = t0 + tl;
       const float zx = obs[2 * t], zy = obs[2 * t + 1];
       const int ks = recover_control(m, obs[2 * t + 2] - zx, obs[2 * t + 3] - zy);
-      float term;
-      policy_terms<CAP_MAX_U>(m, zx, zy, ks, m.gx[g], m.gy[g], m.beta + b, 1, &term);
-      sh.ell[tl * J + j] = term;
+      sh.ell[tl * J + j] = policy_term_one(m, zx, zy, ks, m.gx[g], m.gy[g], m.beta[b]);
     }
     __syncthreads();
 #pragma unroll
