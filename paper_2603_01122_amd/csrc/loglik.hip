@@ -193,32 +193,48 @@ __global__ void __launch_bounds__(kLLThreads)
   }
 }
 
-// Fixed-order second stage: goals sum over tracks; log beta over (track, goal)
-// or, per track, over goals.
-__global__ void loglik_reduce_kernel(int N, int G, int B, int per_track,
-                                     const double* __restrict__ ws_g,
-                                     const double* __restrict__ ws_b, double* __restrict__ dgoals,
-                                     double* __restrict__ dlog_beta) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 2 * G) {
-    const int g = i >> 1, c = i & 1;
-    double s = 0.0;
-    for (int n = 0; n < N; ++n) s += ws_g[((size_t)n * G + g) * 2 + c];
-    dgoals[i] = s;
+// Fixed-order second stage.  Long sums -- the goals over tracks, a shared log
+// beta over (track, goal) -- take one block per output: thread t adds terms
+// t, t + 256, ... in ascending order, then a fixed tree combines the 256
+// partials.  Per-track log beta (a sum over the goals only) takes one thread
+// per output.  Every order is fixed, so results are bitwise reproducible.
+constexpr int kSumThreads = 256;
+
+__global__ void __launch_bounds__(kSumThreads)
+    loglik_sum_kernel(int N, int G, int B, const double* __restrict__ ws_g,
+                      const double* __restrict__ ws_b, double* __restrict__ dgoals,
+                      double* __restrict__ dlog_beta) {
+  __shared__ double red[kSumThreads];
+  const int o = blockIdx.x;
+  double s = 0.0;
+  if (o < 2 * G) {
+    const int g = o >> 1, c = o & 1;
+    for (int n = threadIdx.x; n < N; n += kSumThreads) s += ws_g[((size_t)n * G + g) * 2 + c];
+  } else {
+    const int jb = o - 2 * G;
+    const int total = N * G;  // term i = n G + g
+    for (int i = threadIdx.x; i < total; i += kSumThreads) s += ws_b[(size_t)i * B + jb];
   }
-  const int nb = per_track ? N * B : B;
-  const int jb = i - 2 * G;
-  if (jb >= 0 && jb < nb) {
-    double s = 0.0;
-    if (per_track) {
-      const int n = jb / B, b = jb - n * B;
-      for (int g = 0; g < G; ++g) s += ws_b[((size_t)n * G + g) * B + b];
-    } else {
-      for (int n = 0; n < N; ++n)
-        for (int g = 0; g < G; ++g) s += ws_b[((size_t)n * G + g) * B + jb];
-    }
-    dlog_beta[jb] = s;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) {
+    if (o < 2 * G) dgoals[o] = red[0];
+    else dlog_beta[o - 2 * G] = red[0];
+  }
+}
+
+__global__ void loglik_track_beta_kernel(int N, int G, int B, const double* __restrict__ ws_b,
+                                         double* __restrict__ dlog_beta) {
+  const int jb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jb >= N * B) return;
+  const int n = jb / B, b = jb - n * B;
+  double s = 0.0;
+  for (int g = 0; g < G; ++g) s += ws_b[((size_t)n * G + g) * B + b];
+  dlog_beta[jb] = s;
 }
 
 static cap_status make_ll_args(int32_t K, double speed, double dt, const float* tracks,
@@ -305,9 +321,13 @@ extern "C" cap_status cap_loglik_backward(int32_t K, double speed, double dt,
     }
     CAP_HIP(hipGetLastError());
   }
-  const int outs = 2 * G + (per_track_beta ? N * B : B);
-  hipLaunchKernelGGL(loglik_reduce_kernel, dim3((outs + 255) / 256), dim3(256), 0, s, N, G, B,
-                     a.per_track, ws_g, ws_b, dgoals_dev, dlog_beta_dev);
+  // with N = 0 the sums are empty: the kernels write zeros
+  const int long_sums = 2 * G + (per_track_beta ? 0 : B);
+  hipLaunchKernelGGL(loglik_sum_kernel, dim3(long_sums), dim3(kSumThreads), 0, s, N, G, B, ws_g,
+                     ws_b, dgoals_dev, dlog_beta_dev);
+  if (per_track_beta && N > 0)
+    hipLaunchKernelGGL(loglik_track_beta_kernel, dim3((N * B + 255) / 256), dim3(256), 0, s, N, G,
+                       B, ws_b, dlog_beta_dev);
   CAP_HIP(hipGetLastError());
   return CAP_OK;
 }
