@@ -401,7 +401,7 @@ def main():
                     help="also run one plain copy of this many MiB (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no "
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the library has no "
               "multi-GPU path; humans would be sharded across GPUs with no exchange step.",
               file=sys.stderr)
         sys.exit(2)

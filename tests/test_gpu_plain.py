@@ -1,6 +1,6 @@
 """GPU parity of the single-human entry points against the FP64 oracle.
 
-Bars (spec tolerances):
+Bars (the accuracy targets of the prediction):
 * histograms: identical except where a heading CDF tie falls within 1e-6 --
   every particle whose GPU heading/pair sequence differs from the oracle's must
   be explained by such a tie at its first difference (oracle.tie_check), and
