@@ -283,3 +283,100 @@ def test_tie_check_classifies(orc):
     # an explained change: the window is wide enough to cover the whole CDF
     st, first = orc.tie_check(other_pair=out["trace_pair"], other_k=bad, window=2.0, **kw)
     assert st[10] == 1
+
+
+def _replay(h, belief, torch_philox, i, H, seed, hid, cyc):
+    """Independent replay of particle i (NumPy FP64, PyTorch's Philox): its pair
+    j with the pair CDF P and u, and per step the heading k, the normalised CDF
+    C / C[-1] and u (Alg. 1 with the documented counters and lattice)."""
+    x0, y0, cell, nx, ny = h.grid
+    q = cell / 65536
+    th = 2 * math.pi * np.arange(h.K) / h.K
+    Sx = np.rint(h.speed * h.dt * np.cos(th) / q)
+    Sy = np.rint(h.speed * h.dt * np.sin(th) / q)
+    P = np.cumsum(belief.reshape(-1))
+    up = u_of(torch_philox, seed, i, 0, hid, 2 * cyc, 0)
+    j = int(np.argmax(up < P)) if up < P[-1] else int(np.flatnonzero(belief.reshape(-1) > 0)[-1])
+    g, b = divmod(j, h.B)
+    GX = np.rint((float(h.goals[g][0]) - x0) / q)
+    GY = np.rint((float(h.goals[g][1]) - y0) / q)
+    X, Y = np.rint((h.start[0] - x0) / q), np.rint((h.start[1] - y0) / q)
+    steps = []
+    for t in range(1, H + 1):
+        d = np.hypot((X + Sx - GX) * q, (Y + Sy - GY) * q)
+        C = np.cumsum(np.exp(-float(h.beta[b]) * (d - d.min())))
+        u = u_of(torch_philox, seed, i, (t - 1) // 4, hid, 2 * cyc + 1, (t - 1) % 4)
+        k = int(np.argmax(u * C[-1] < C)) if u * C[-1] < C[-1] else h.K - 1
+        steps.append((k, C / C[-1], u))
+        X, Y = X + Sx[k], Y + Sy[k]
+    return j, P, up, steps
+
+
+def test_tie_check_window_boundaries(orc, torch_philox):
+    """orc_tie_check, pinned on both sides of every window it applies.  For a
+    difference at heading step t the other choice ko must lie across CDF
+    boundaries that are all within `window` of u: for ko > k the farthest is
+    C[ko-1]/C[-1] - u, for ko < k it is u - C[ko]/C[-1].  For each particle and
+    ko in {k-2, k-1, k+1, k+2} that distance is computed here independently;
+    the checker must report status 1 (explained) at a window just above it and
+    2 at a window just below it, and the first difference at step t; the pair
+    draw likewise against pair_window.  An off-by-one boundary, a flipped sign
+    or a swapped window fails one side."""
+    h = scenes.config1().humans[0]
+    belief = scenes.random_belief(h.G, h.B, seed=6)
+    N, H, seed, hid, cyc = 48, 6, 3, 4, 2
+    kw = dict(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals, grid=h.grid,
+              z0=h.start, belief=belief, N=N, H=H, seed=seed, human=hid, cycle=cyc)
+    out = orc.predict(trace=True, **kw)
+    rng = np.random.default_rng(11)
+    checked = {1: 0, 2: 0}
+    for i in range(N):
+        j, P, up, steps = _replay(h, belief, torch_philox, i, H, seed, hid, cyc)
+        assert out["trace_pair"][i] == j
+        assert [s[0] for s in steps] == list(out["trace_k"][i])
+        t = int(rng.integers(1, H + 1))
+        k, Cn, u = steps[t - 1]
+        for ko in (k - 2, k - 1, k + 1, k + 2):
+            if not 0 <= ko < h.K:
+                continue
+            dist = Cn[ko - 1] - u if ko > k else u - Cn[ko]
+            assert dist >= 0
+            other = out["trace_k"].copy()
+            other[i, t - 1] = ko
+            for win, want in ((dist * (1 + 1e-6) + 1e-15, 1), (dist * (1 - 1e-6) - 1e-15, 2)):
+                if win < 0:
+                    continue
+                st, first = orc.tie_check(other_pair=out["trace_pair"][i:i + 1],
+                                          other_k=other[i:i + 1], window=win, idx=[i], **kw)
+                assert st[0] == want and first[0] == t, (i, t, k, ko, dist, win)
+                checked[want] += 1
+        # the pair draw: the other implementation picked a neighbouring pair
+        for jo in (j - 2, j - 1, j + 1, j + 2):
+            if not 0 <= jo < P.size:
+                continue
+            dist = P[jo - 1] - up if jo > j else up - P[jo]
+            other = out["trace_pair"].copy()
+            other[i] = jo
+            for win, want in ((dist * (1 + 1e-6) + 1e-15, 1), (dist * (1 - 1e-6) - 1e-15, 2)):
+                if win < 0:
+                    continue
+                st, first = orc.tie_check(other_pair=other[i:i + 1],
+                                          other_k=out["trace_k"][i:i + 1], pair_window=win,
+                                          window=1.0, idx=[i], **kw)
+                assert st[0] == want and first[0] == 0, (i, j, jo, dist, win)
+    assert checked[1] > 50 and checked[2] > 50
+    # the target's 1e-6 window itself: distances found above straddle it
+    near = []
+    for i in range(N):
+        _, _, _, steps = _replay(h, belief, torch_philox, i, H, seed, hid, cyc)
+        for t, (k, Cn, u) in enumerate(steps, 1):
+            if k + 1 < h.K:
+                near.append((Cn[k] - u, i, t, k + 1))
+    # an unexplained change stays unexplained at the target window unless its
+    # boundary really is within 1e-6 of u
+    for dist, i, t, ko in sorted(near)[:5] + sorted(near)[-3:]:
+        other = out["trace_k"].copy()
+        other[i, t - 1] = ko
+        st, _ = orc.tie_check(other_pair=out["trace_pair"][i:i + 1], other_k=other[i:i + 1],
+                              window=1e-6, idx=[i], **kw)
+        assert st[0] == (1 if dist <= 1e-6 else 2)
