@@ -2,16 +2,17 @@
 // in the log form of Sec. III-B, for one human per thread block.
 #pragma once
 
+#include "dfloat.hpp"
 #include "model.hpp"
 
 namespace capred {
 
 constexpr int kBeliefThreads = 256;
-constexpr int kBeliefChunk = 4;   // observed transitions staged in LDS at a time (8 KiB: the
+constexpr int kBeliefChunk = 2;   // observed transitions staged in LDS at a time (8 KiB: the
                                   // update fits beside the rollout blocks of a busy CU)
 
 struct BeliefShared {
-  float ell[kBeliefChunk * CAP_MAX_J];
+  double ell[kBeliefChunk * CAP_MAX_J];
   double red[kBeliefThreads / 64];
 };
 
@@ -19,7 +20,7 @@ struct BeliefShared {
 // heading k* = argmax_k <dz, (cos, sin)theta_k> with the lowest k on ties, then
 // the speed whose step v_s dt is nearest to that projection (lowest s on
 // ties); returns u* = s* K + k*, or -1 when the displacement is below 1e-9 m.
-__device__ __forceinline__ int recover_control(const BeliefModel& m, float dx, float dy) {
+__host__ __device__ __forceinline__ int recover_control(const BeliefModel& m, float dx, float dy) {
   if (fmaf(dx, dx, dy * dy) < 1e-18f) return -1;
   int ks = 0;
   float best = -INFINITY;
@@ -42,7 +43,10 @@ __device__ __forceinline__ int recover_control(const BeliefModel& m, float dx, f
   return ss * m.K + ks;
 }
 
-// log pi(u* | z; beta_b, g) for every b over the U controls, FP32.
+// log pi(u* | z; beta_b, g) for every b over the U controls in plain FP32 (the
+// trajectory log-likelihood's terms: its bar is relative to |LL|, a sum of
+// hundreds of terms, so FP32 logits meet it; the posterior update uses the
+// compensated policy_term_one below).
 // Delta_u = |a + s_u| - |a| with a = z - g carried as an unevaluated sum
 // (hi + lo, exact subtraction), from the cancellation-free quotient
 // (2 a.s_u + |s_u|^2) / (|a + s_u| + |a|); then l_u = -beta Delta_u and
@@ -87,38 +91,42 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
   }
 }
 
-// policy_terms for one beta without a per-control array (so that large
-// control sets stay out of scratch memory): the smallest Delta in a first pass
-// over the controls, the exponential sum in a second pass that recomputes
-// each Delta with the same arithmetic (bit-identical to policy_terms).
-__device__ __forceinline__ float policy_term_one(const BeliefModel& m, float zx, float zy, int ks,
-                                                 float gx, float gy, float beta) {
-  if (ks < 0) return 0.f;
-  const int U = m.U;
-  const float ax = zx - gx, bx = ax - zx;
-  const float ax_lo = (zx - (ax - bx)) + (-gx - bx);
-  const float ay = zy - gy, by = ay - zy;
-  const float ay_lo = (zy - (ay - by)) + (-gy - by);
-  const float D2 = fmaf(ax, ax, ay * ay);
-  const float D = sqrtf(D2);
-  const float ax2 = ax + ax, ay2 = ay + ay;
-  auto delta = [&](int k) {
-    const float corr = fmaf(2.f * ax_lo, m.sx[k], fmaf(2.f * ay_lo, m.sy[k], m.s2[k]));
-    const float n = fmaf(ax2, m.sx[k], fmaf(ay2, m.sy[k], corr));
-    const float d = sqrtf(fmaxf(D2 + n, 0.f));
-    return n / (d + D);
-  };
-  float dmin = INFINITY, dks = 0.f;
-  for (int k = 0; k < U; ++k) {
-    const float dl = delta(k);
-    dmin = fminf(dmin, dl);
-    if (k == ks) dks = dl;
+// log pi(u* | z; beta, g) of the posterior update, for one beta.  The update
+// multiplies up to thousands of these terms into a posterior whose log must
+// stay within 1e-5 of the exact one, and a term's rounding error grows with
+// beta |s| (about 15 at beta = 100 and a 0.15 m step): plain FP32 logits err
+// by a few 1e-6 per transition.  So the logits are evaluated in compensated
+// FP32 (hi + lo pairs, about 48 bits): a = z - g exactly, |a|^2,
+// n_u = 2 a.s_u + |s_u|^2 and Delta_u = n_u / (|a + s_u| + |a|) (the
+// cancellation-free difference of the two distances), l_u = -beta Delta_u;
+// each l_u is rounded once to FP64, where the log-sum-exp over the controls
+// runs (single pass with a running maximum).  log pi = (l_{u*} - max l) -
+// log sum exp(l - max l).  Error per term: a few 1e-13 of beta |s| plus the
+// FP64 exponentials', against 1e-5 over the whole history.
+__host__ __device__ __forceinline__ double policy_term_one(const BeliefModel& m, float zx, float zy, int ks,
+                                                  float gx, float gy, float beta) {
+  if (ks < 0) return 0.0;
+  const dfl ax = two_sum(zx, -gx), ay = two_sum(zy, -gy);
+  const dfl D2 = df_add(df_mul(ax, ax), df_mul(ay, ay));
+  const dfl D = df_sqrt(D2);
+  double mx = -INFINITY, s = 0.0, lks = 0.0;
+  for (int k = 0; k < m.U; ++k) {
+    const float sx = m.sx[k], sy = m.sy[k];
+    const dfl s2 = df_add(two_prod(sx, sx), two_prod(sy, sy));
+    const dfl dot = df_add(df_mul_f(ax, sx), df_mul_f(ay, sy));
+    const dfl n = df_add(dfl{2.f * dot.hi, 2.f * dot.lo}, s2);
+    const dfl d = df_sqrt(df_add(D2, n));
+    const dfl delta = df_div(n, df_add(d, D));
+    const double l = -df_to_double(df_mul_f(delta, beta));
+    if (k == ks) lks = l;
+    if (l > mx) {
+      s = s * exp(mx - l) + 1.0;
+      mx = l;
+    } else {
+      s += exp(l - mx);
+    }
   }
-  const float nbt = -beta;
-  const float mx = nbt * dmin;
-  float s = 0.f;
-  for (int k = 0; k < U; ++k) s += exp_nonpos(nbt * delta(k) - mx);
-  return (nbt * dks - mx) - logf(s);
+  return (lks - mx) - log(s);
 }
 
 __device__ __forceinline__ double block_reduce(double v, bool is_max, double* red) {
@@ -162,7 +170,7 @@ __device__ void belief_update_block(const BeliefModel& m, const float* __restric
     for (int r = 0; r < kPerThread; ++r) {
       const int j = tid + r * nthr;
       if (j < J)
-        for (int tl = 0; tl < nt; ++tl) acc[r] += (double)sh.ell[tl * J + j];
+        for (int tl = 0; tl < nt; ++tl) acc[r] += sh.ell[tl * J + j];
     }
     __syncthreads();
   }

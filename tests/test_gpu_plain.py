@@ -6,9 +6,8 @@ Bars (the accuracy targets of the prediction):
   be explained by such a tie at its first difference (oracle.tie_check), and
   per step sum_c |count_gpu - count_oracle| <= 2 * (flagged particles whose
   first difference is at or before that step); occupancy TV <= 1e-3;
-* posterior: |log b_gpu - log b_oracle| <= 1e-5 max(1, |log b_oracle|) (the
-  plain relative error 1e-5 of b wherever b >= 1/e; the tests below with
-  moderate posteriors also meet the unscaled 1e-5);
+* posterior: relative error 1e-5, i.e. |log b_gpu - log b_oracle| <= 1e-5 for
+  every pair, however small its posterior;
 * log-likelihood: |LL_gpu - LL_oracle| <= 1e-5 max(1, |LL_oracle|);
   gradients: norm-wise relative error <= 1e-5;
 * integer outputs (Philox words, normalisation bits, simulated lattices): exact.
@@ -135,10 +134,9 @@ def test_belief_update_long_history_and_stationary(orc, cap):
     cap.belief_update(cap.model_of(h), torch.tensor(obs, device="cuda"), lb)
     lb_o, _, _ = orc.belief_update(K=h.K, speed=h.speed, dt=h.dt, beta=h.beta, goals=h.goals,
                                    obs=obs)
-    # absolute error relative to the posterior's dynamic range (FP32 per-step terms)
-    err = np.abs(lb.cpu().numpy() - lb_o)
-    finite = lb_o > -700
-    assert np.max(err[finite] / np.maximum(1.0, np.abs(lb_o[finite]))) <= 1e-5
+    err = np.max(np.abs(lb.cpu().numpy() - lb_o))
+    print(f"152 transitions: max |dlog b| = {err:.3e}, min log b = {lb_o.min():.1f}")
+    assert err <= 1e-5
 
 
 @pytest.mark.parametrize("cfg", ["config1", "config2"])
