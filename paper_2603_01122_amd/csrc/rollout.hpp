@@ -100,9 +100,10 @@ __host__ __device__ constexpr size_t window_lds_bytes(int cap, int particles_per
 // array of CAP_MAX_U float4 that receives (fx, fy, s2) of every control, read
 // per lane for the block recomputation and the step (unused otherwise).
 template <int KT, int P, bool SHIFT, bool MS>
-__device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_lo,
-                             uint32_t seed_hi, TileShared& sh, uint32_t* win, int cap,
-                             float4* ctl) {
+__device__ __forceinline__ void rollout_tile_body(const RolloutDesc& d, int64_t first,
+                                                  uint32_t seed_lo, uint32_t seed_hi,
+                                                  TileShared& sh, uint32_t* win, int cap,
+                                                  float4* ctl) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int J = d.G * d.B;
@@ -262,6 +263,24 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
     }
   }
   __syncthreads();
+}
+
+// A tile of one human.  The shifted exponent is a property of the human
+// (d.shift: beta * step too large for the unshifted exp2), not of the launch:
+// a launch compiled with SHIFT also carries the unshifted body and takes it,
+// uniformly per tile, for humans that do not need the shift, so that their
+// draws are the same bits whichever humans share the launch.
+template <int KT, int P, bool SHIFT, bool MS>
+__device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first, uint32_t seed_lo,
+                                             uint32_t seed_hi, TileShared& sh, uint32_t* win,
+                                             int cap, float4* ctl) {
+  if constexpr (SHIFT) {
+    if (!d.shift) {
+      rollout_tile_body<KT, P, false, MS>(d, first, seed_lo, seed_hi, sh, win, cap, ctl);
+      return;
+    }
+  }
+  rollout_tile_body<KT, P, SHIFT, MS>(d, first, seed_lo, seed_hi, sh, win, cap, ctl);
 }
 
 }  // namespace capred

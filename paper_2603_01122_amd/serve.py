@@ -8,6 +8,11 @@ launch, normalisation).  Humans arrive and leave while cycles are in flight:
 * admission -- an arriving human waits until a slot is free and the particle
   budget (total particles in flight per cycle, which bounds the cycle time)
   has room for its N; it then joins at the next cycle boundary;
+* departure -- a departing human leaves the next cycle at once, but its slot
+  is only reused once every cycle in flight that included it has completed:
+  a newcomer's buffer views are shaped by its own G, B, H and grid, so its
+  ring entries and belief rows can overlap the departed human's, which those
+  cycles are still reading and writing;
 * overlap -- consecutive cycles go to alternating streams and use alternating
   ring entries of every per-cycle buffer, so cycle c+1 can start on the device
   while cycle c is still running; only the tiny belief updates are ordered;
@@ -98,6 +103,9 @@ class Server:
         self.pool_b = torch.zeros((n_slots, ring * max_G * max_B), dtype=torch.float64,
                                   device=device)
         self.free: List[int] = list(range(n_slots))
+        # departed slots and the completion events of the cycles in flight that
+        # still use them; a slot returns to `free` once all have completed
+        self._retiring: List[Tuple[int, List[torch.cuda.Event]]] = []
         self.slot_of: Dict[int, int] = {}
         self.req: Dict[int, HumanRequest] = {}
         self.waiting: collections.deque = collections.deque()
@@ -131,7 +139,11 @@ class Server:
             s = self.slot_of.pop(hid)
             self.plan.retire(s)
             self.in_use -= self.req.pop(hid).N
-            self.free.append(s)
+            busy = [r.done_event for r in self._pending if hid in r.humans]
+            if busy:
+                self._retiring.append((s, busy))
+            else:
+                self.free.append(s)
         else:
             self.waiting = collections.deque(r for r in self.waiting if r.hid != hid)
 
@@ -146,7 +158,18 @@ class Server:
             self.pool_lb[s, :G * B].view(G, B),
             self.pool_b[s, :R * G * B].view(R, G, B))
 
+    def _reclaim(self):
+        """Returns departed slots whose in-flight cycles have all completed."""
+        keep = []
+        for s, evs in self._retiring:
+            if all(e.query() for e in evs):
+                self.free.append(s)
+            else:
+                keep.append((s, evs))
+        self._retiring = keep
+
     def _admit_waiting(self):
+        self._reclaim()
         kept = collections.deque()
         while self.waiting:
             r = self.waiting.popleft()
@@ -241,6 +264,12 @@ class Server:
         b = self._views(s, r)
         e = cycle % self.ring
         return (b.counts[e], None if b.probs is None else b.probs[e], b.offgrid[e], b.belief[e])
+
+    def log_belief(self, hid: int) -> torch.Tensor:
+        """`hid`'s log posterior [G, B] after the newest cycle that has run
+        (read it once that cycle is complete, e.g. after drain())."""
+        s = self.slot_of[hid]
+        return self._views(s, self.req[hid]).log_belief
 
     def close(self):
         self.plan.sync()
