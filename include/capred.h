@@ -221,6 +221,26 @@ cap_status cap_loglik_backward(int32_t K, double speed, double dt, const float* 
                                size_t ws_bytes, void* stream);
 size_t cap_loglik_backward_workspace(int32_t N, int32_t G, int32_t B, int32_t per_track_beta);
 
+/* cap_loglik_backward without a workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, layout, results (bit for bit) and
+ * errors as cap_loglik_backward minus ws_dev / ws_bytes; the partial sums go
+ * to a library-owned static device array of CAP_LOGLIK_SCRATCH_BYTES, one per
+ * device, held until the process ends (its address is looked up once per
+ * device, with that device current, on the first call there).
+ *   Limit: cap_loglik_backward_workspace(N, G, B, per_track_beta) must not
+ *   exceed CAP_LOGLIK_SCRATCH_BYTES (e.g. N * G <= 47662 at B = 9), else
+ *   CAP_E_CAPACITY before any launch.  Calls no allocator.
+ *   Calls that overlap on one device (different streams, or host threads
+ *   without ordering) share the array and race: order them on one stream. */
+#define CAP_LOGLIK_SCRATCH_BYTES ((size_t)4 << 20)
+cap_status cap_loglik_backward_noalloc(int32_t K, double speed, double dt,
+                                       const float* tracks_dev, const int32_t* lengths_dev,
+                                       int32_t N, int32_t Tmax, const float* goals_dev,
+                                       int32_t G, const float* log_beta_dev, int32_t B,
+                                       int32_t per_track_beta, const double* dLL_dev,
+                                       double* dgoals_dev, double* dlog_beta_dev, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched many-human prediction: one persistent launch per cycle for all
  * humans (replacing the sequential per-human loop of Sec. IV-B), captured in

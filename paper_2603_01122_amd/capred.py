@@ -106,12 +106,15 @@ _sig("cap_loglik", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i3
 _sig("cap_loglik_backward", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _i32,
      _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("cap_loglik_backward_workspace", _sz, _i32, _i32, _i32, _i32)
+_sig("cap_loglik_backward_noalloc", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _i32,
+     _i32, _vp, _vp, _vp, _vp)
 _sig("cap_philox_blocks", _i32, _i64, _u32, _u32, _u32, _u32, _u64, _vp, _vp)
 _sig("cap_probe", _i32, _i32, _i64, _i32, _vp, _vp)
 _sig("cap_copy", _i32, _vp, _vp, _sz, _vp)
 EXPORTED = ["cap_probe", "cap_copy", "cap_philox_blocks", "cap_abi_version", "cap_last_error", "cap_device_cu_count", "cap_belief_update",
             "cap_belief_reset", "cap_predict_occupancy", "cap_normalize", "cap_simulate_tracks",
             "cap_loglik", "cap_loglik_backward", "cap_loglik_backward_workspace",
+            "cap_loglik_backward_noalloc",
             "cap_smooth_occupancy", "cap_union_max", "cap_mppi_step"]
 if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_create", _i32, C.POINTER(cap_plan_config), C.POINTER(_vp))
@@ -426,6 +429,21 @@ def loglik_backward(K, speed, dt, tracks, lengths, goals, log_beta, dLL, stream=
                                     ws.data_ptr(), ws_bytes, _stream(stream)),
            "cap_loglik_backward")
     return dg, db
+
+
+def loglik_backward_noalloc(K, speed, dt, tracks, lengths, goals, log_beta, dLL, dgoals,
+                            dlog_beta, stream=None):
+    """loglik_backward into caller-provided outputs (dgoals [G,2], dlog_beta
+    shaped like log_beta, both FP64) through the library's allocation-free
+    entry point: nothing is allocated on the device by this call."""
+    args = _ll_args(K, speed, dt, tracks, lengths, goals, log_beta)
+    N, G, B = args[5], args[8], args[10]
+    _ptr(dLL, torch.float64, "dLL", (N, B, G))
+    _ptr(dgoals, torch.float64, "dgoals", (G, 2))
+    _ptr(dlog_beta, torch.float64, "dlog_beta", tuple(log_beta.shape))
+    _check(_lib.cap_loglik_backward_noalloc(*args, dLL.data_ptr(), dgoals.data_ptr(),
+                                            dlog_beta.data_ptr(), _stream(stream)),
+           "cap_loglik_backward_noalloc")
 
 
 class LogLik(torch.autograd.Function):

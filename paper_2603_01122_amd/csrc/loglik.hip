@@ -5,6 +5,8 @@
 // reduced across the wave by a fixed butterfly, so results are bitwise
 // reproducible.  The adjoint writes per-(track, goal) partials to the
 // workspace and a second kernel sums them in a fixed order (no atomics).
+#include <mutex>
+
 #include "belief.hpp"
 
 namespace capred {
@@ -290,23 +292,13 @@ extern "C" size_t cap_loglik_backward_workspace(int32_t N, int32_t G, int32_t B,
   return (size_t)N * G * (2 + B) * sizeof(double);
 }
 
-extern "C" cap_status cap_loglik_backward(int32_t K, double speed, double dt,
-                                          const float* tracks_dev, const int32_t* lengths_dev,
-                                          int32_t N, int32_t Tmax, const float* goals_dev,
-                                          int32_t G, const float* log_beta_dev, int32_t B,
-                                          int32_t per_track_beta, const double* dLL_dev,
-                                          double* dgoals_dev, double* dlog_beta_dev, void* ws_dev,
-                                          size_t ws_bytes, void* stream) {
-  LLArgs a;
-  cap_status st = make_ll_args(K, speed, dt, tracks_dev, lengths_dev, N, Tmax, goals_dev, G,
-                               log_beta_dev, B, per_track_beta, &a);
-  if (st != CAP_OK) return st;
-  if (!dgoals_dev || !dlog_beta_dev) return fail(CAP_E_INVALID, "dgoals/dlog_beta is NULL");
-  if (N > 0 && !dLL_dev) return fail(CAP_E_INVALID, "dLL is NULL");
-  const size_t need = cap_loglik_backward_workspace(N, G, B, per_track_beta);
-  if (need > 0 && (!ws_dev || ws_bytes < need))
-    return fail(CAP_E_WORKSPACE, "workspace smaller than cap_loglik_backward_workspace()");
-  hipStream_t s = as_stream(stream);
+namespace capred {
+
+// The adjoint's launches with the partial sums in ws (cap_loglik_backward_workspace bytes).
+static cap_status loglik_backward_launch(const LLArgs& a, int32_t per_track_beta,
+                                         const double* dLL_dev, double* dgoals_dev,
+                                         double* dlog_beta_dev, void* ws_dev, hipStream_t s) {
+  const int32_t N = a.N, G = a.G, B = a.B;
   double* ws_g = static_cast<double*>(ws_dev);
   double* ws_b = ws_g + (size_t)N * G * 2;
   if (N > 0) {
@@ -330,4 +322,79 @@ extern "C" cap_status cap_loglik_backward(int32_t K, double speed, double dt,
                        B, ws_b, dlog_beta_dev);
   CAP_HIP(hipGetLastError());
   return CAP_OK;
+}
+
+// Device-resident partial sums of the allocation-free adjoint.  Each device
+// holds its own copy (until the process ends); host code reaches it only
+// through the per-device address from hipGetSymbolAddress, never through the
+// array's name, which on the host is a stand-in and not a device address.
+__device__ __align__(256) double loglik_scratch[CAP_LOGLIK_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// loglik_scratch's address on the current device (looked up once per device).
+static cap_status scratch_of_current_device(void** out) {
+  int dev = 0;
+  CAP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CAP_E_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    CAP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(loglik_scratch)));
+    if (!p) return fail(CAP_E_HIP, "hipGetSymbolAddress returned no address for the scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CAP_OK;
+}
+
+}  // namespace capred
+
+extern "C" cap_status cap_loglik_backward(int32_t K, double speed, double dt,
+                                          const float* tracks_dev, const int32_t* lengths_dev,
+                                          int32_t N, int32_t Tmax, const float* goals_dev,
+                                          int32_t G, const float* log_beta_dev, int32_t B,
+                                          int32_t per_track_beta, const double* dLL_dev,
+                                          double* dgoals_dev, double* dlog_beta_dev, void* ws_dev,
+                                          size_t ws_bytes, void* stream) {
+  LLArgs a;
+  cap_status st = make_ll_args(K, speed, dt, tracks_dev, lengths_dev, N, Tmax, goals_dev, G,
+                               log_beta_dev, B, per_track_beta, &a);
+  if (st != CAP_OK) return st;
+  if (!dgoals_dev || !dlog_beta_dev) return fail(CAP_E_INVALID, "dgoals/dlog_beta is NULL");
+  if (N > 0 && !dLL_dev) return fail(CAP_E_INVALID, "dLL is NULL");
+  const size_t need = cap_loglik_backward_workspace(N, G, B, per_track_beta);
+  if (need > 0 && (!ws_dev || ws_bytes < need))
+    return fail(CAP_E_WORKSPACE, "workspace smaller than cap_loglik_backward_workspace()");
+  return loglik_backward_launch(a, per_track_beta, dLL_dev, dgoals_dev, dlog_beta_dev, ws_dev,
+                                as_stream(stream));
+}
+
+extern "C" cap_status cap_loglik_backward_noalloc(int32_t K, double speed, double dt,
+                                                  const float* tracks_dev,
+                                                  const int32_t* lengths_dev, int32_t N,
+                                                  int32_t Tmax, const float* goals_dev, int32_t G,
+                                                  const float* log_beta_dev, int32_t B,
+                                                  int32_t per_track_beta, const double* dLL_dev,
+                                                  double* dgoals_dev, double* dlog_beta_dev,
+                                                  void* stream) {
+  LLArgs a;
+  cap_status st = make_ll_args(K, speed, dt, tracks_dev, lengths_dev, N, Tmax, goals_dev, G,
+                               log_beta_dev, B, per_track_beta, &a);
+  if (st != CAP_OK) return st;
+  if (!dgoals_dev || !dlog_beta_dev) return fail(CAP_E_INVALID, "dgoals/dlog_beta is NULL");
+  if (N > 0 && !dLL_dev) return fail(CAP_E_INVALID, "dLL is NULL");
+  if (cap_loglik_backward_workspace(N, G, B, per_track_beta) > CAP_LOGLIK_SCRATCH_BYTES)
+    return fail(CAP_E_CAPACITY,
+                "N * G * (2 + B) * 8 bytes exceed CAP_LOGLIK_SCRATCH_BYTES; use cap_loglik_backward "
+                "with a caller workspace");
+  void* scratch = nullptr;
+  st = scratch_of_current_device(&scratch);
+  if (st != CAP_OK) return st;
+  // every partial-sum slot the launches read is written first (one per (track,
+  // goal) item), so the previous call's contents need no clearing
+  return loglik_backward_launch(a, per_track_beta, dLL_dev, dgoals_dev, dlog_beta_dev, scratch,
+                                as_stream(stream));
 }
