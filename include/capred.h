@@ -341,6 +341,18 @@ cap_status cap_plan_sync(cap_plan* plan);
  * blocks). */
 cap_status cap_plan_stats(const cap_plan* plan, int64_t* particles, int64_t* particle_steps,
                           int32_t* tiles);
+/* Union stage (Sec. IV-B: the planner reads one occupancy map of all humans):
+ * from the next cycle on, every cycle also writes the point-wise maximum of
+ * the probabilities (count / N, or the smoothed ones) of each active slot
+ * whose grid equals `frame` (same origin, cell, nx, ny) and that has probs_dev,
+ * into union_dev[cycle % ring][t][ny][nx] for t < H (a slot contributes its
+ * steps t < min(H, its horizon); cells that no such slot reaches are 0).  It is
+ * computed inside the cycle's graph: cleared with the grids, then raised by
+ * the normalisation / smoothing stages with integer atomic max on the FP32
+ * bits (exact, independent of order).  cap_plan_run_plain does the same in its
+ * per-human launches.  union_dev: caller-owned [ring][H][ny][nx] FP32;
+ * NULL switches the stage off.  Errors: bad frame, H outside [1, 4096]. */
+cap_status cap_plan_set_union(cap_plan* plan, const cap_grid* frame, int32_t H, float* union_dev);
 /* Effective tuning of the plan (after defaults are resolved). */
 cap_status cap_plan_tuning(const cap_plan* plan, cap_plan_config* out);
 /* The cut of a cycle's particles into the persistent launch's tiles (host

@@ -126,6 +126,7 @@ if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_stage_obs", _i32, _vp, _i32, C.POINTER(C.c_float), _i32)
     _sig("cap_plan_run", _i32, _vp, _u64, _u32, _vp)
     _sig("cap_plan_run_plain", _i32, _vp, _u64, _u32, _vp)
+    _sig("cap_plan_set_union", _i32, _vp, C.POINTER(cap_grid), _i32, _vp)
     _sig("cap_plan_sync", _i32, _vp)
     _sig("cap_plan_stats", _i32, _vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32))
     _sig("cap_plan_tuning", _i32, _vp, C.POINTER(cap_plan_config))
@@ -134,7 +135,8 @@ if hasattr(_lib, "cap_plan_create"):
     EXPORTED += ["cap_plan_replay_rollout", "cap_plan_create", "cap_plan_destroy", "cap_plan_set_slot",
                  "cap_plan_clear_slot", "cap_plan_stage_obs", "cap_plan_run",
                  "cap_plan_run_plain", "cap_plan_sync", "cap_plan_stats", "cap_plan_tuning",
-                 "cap_plan_set_speed_mask", "cap_plan_reset_belief", "cap_plan_tile_split"]
+                 "cap_plan_set_speed_mask", "cap_plan_reset_belief", "cap_plan_tile_split",
+                 "cap_plan_set_union"]
 
 
 def _check(rc: int, what: str):
@@ -582,6 +584,19 @@ class Plan:
 
     def reset_belief(self, slot: int):
         _check(_lib.cap_plan_reset_belief(self._h, slot), "cap_plan_reset_belief")
+
+    def set_union(self, frame, H: int, union: Optional[torch.Tensor]):
+        """From the next cycle on, write the point-wise maximum of the
+        probabilities of the slots whose grid is `frame` into union[cycle % ring]
+        ([ring, H, ny, nx] FP32); union=None switches the stage off."""
+        if union is None:
+            _check(_lib.cap_plan_set_union(self._h, None, 0, None), "cap_plan_set_union")
+            self._union = None
+            return
+        g = grid_c(frame)
+        ptr = _ptr(union, torch.float32, "union", (self.ring, H, int(frame[4]), int(frame[3])))
+        _check(_lib.cap_plan_set_union(self._h, C.byref(g), H, ptr), "cap_plan_set_union")
+        self._union = union
 
     def stage(self, slot: int, xy):
         a = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)

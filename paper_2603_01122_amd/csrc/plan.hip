@@ -45,6 +45,7 @@ struct SlotDev {
   int32_t full_clear;        // 1: the ring entry's content is unknown (clear every cell)
   int32_t kt_begin[kTileKinds];  // per tile kind: tickets of earlier slots (within the kind)
   int32_t kt_first[kTileKinds];  // per tile kind: first particle of this slot's tiles
+  int32_t in_union;              // 1: this slot's probabilities join the union grid
 };
 
 struct CycleHeader {
@@ -54,7 +55,25 @@ struct CycleHeader {
   int32_t tile_begin[CAP_MAX_SLOTS + 1];   // per-human launches: prefix of P-sized tiles
   int32_t step_begin[CAP_MAX_SLOTS + 1];   // prefix of horizons (one work item per step)
   int32_t smooth_begin[CAP_MAX_SLOTS + 1]; // prefix of smoothing tiles
+  float* union_out;                        // ring entry's union grid [union_H][ny][nx] or null
+  int32_t union_H, union_nx, union_ny;
 };
+
+// Union grid of the humans sharing a frame (Sec. IV-B: one occupancy map of
+// all humans for the planner): the point-wise maximum of their probabilities,
+// accumulated with integer atomic max on the FP32 bit patterns (for values
+// >= 0 the IEEE order is the unsigned-integer order), so the result is exact
+// and independent of the order of contributions.  Cells start at 0 (cleared
+// in the grid-clear kernel) and only nonzero probabilities are sent.
+__device__ __forceinline__ void union_max_at(const CycleHeader* H, int t, size_t cell_in_plane,
+                                             float v) {
+  if (v > 0.f && t <= H->union_H) {
+    const size_t plane = (size_t)H->union_nx * H->union_ny;
+    __hip_atomic_fetch_max(as_global(reinterpret_cast<uint32_t*>(H->union_out)) +
+                               (size_t)(t - 1) * plane + cell_in_plane,
+                           __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
 
 __device__ __forceinline__ const SlotDev* slots_of(const uint8_t* base) {
   return reinterpret_cast<const SlotDev*>(base + sizeof(CycleHeader));
@@ -113,8 +132,8 @@ __device__ __forceinline__ void item_range(const CycleHeader* H, int only, int* 
   *i1 = only >= 0 ? (only < na ? H->step_begin[only + 1] : 0) : H->step_begin[na];
 }
 
-// Clears the counts (and off-grid counters) of every active slot -- or of one
-// -- and resets the tile queues for the rollout that follows.
+// Clears the counts (and off-grid counters) of every active slot (only < 0) --
+// or of slot `only` -- and resets the tile queues for the rollout that follows.
 __global__ void __launch_bounds__(256)
     plan_zero_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int only) {
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
@@ -135,6 +154,15 @@ __global__ void __launch_bounds__(256)
       for (int x = lane; x < r.w; x += 64) p[(size_t)y * sd.rd.nx + x] = 0u;
     if (threadIdx.x == 0 && sd.rd.offgrid) as_global(sd.rd.offgrid)[t - 1] = 0u;
   }
+  // the union grid (the per-human launches clear it with the first human's
+  // clear; a replay of the rollout alone, only = -2, leaves it)
+  if (H->union_out && (only == -1 || only == 0)) {
+    const size_t n = (size_t)H->union_H * H->union_nx * H->union_ny;
+    global_ptr<uint32_t> u = as_global(reinterpret_cast<uint32_t*>(H->union_out));
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+      u[i] = 0u;
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -153,11 +181,15 @@ __global__ void __launch_bounds__(256)
     global_ptr<const uint32_t> q = as_global(static_cast<const uint32_t*>(sd.rd.counts)) + origin;
     global_ptr<float> p = as_global(sd.probs) + origin;
     const float N = (float)sd.rd.N;
+    const bool un = sd.in_union != 0;
+    const size_t corner = (size_t)r.y0 * sd.rd.nx + r.x0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int y = wave; y < r.h; y += nw)
       for (int x = lane; x < r.w; x += 64) {
         const size_t c = (size_t)y * sd.rd.nx + x;
-        p[c] = (float)q[c] / N;
+        const float v = (float)q[c] / N;
+        p[c] = v;
+        if (un) union_max_at(H, t, corner + c, v);
       }
   }
 }
@@ -190,9 +222,12 @@ __global__ void __launch_bounds__(kSmoothThreads)
     const int rem = local - t * tx * ty;
     const int by = rem / tx, bx = rem - by * tx;
     const size_t plane = (size_t)ny * nx;
+    float* un = sd.in_union && t + 1 <= H->union_H
+                    ? H->union_out + (size_t)t * H->union_nx * H->union_ny
+                    : nullptr;
     smooth_block(sd.rd.counts + (size_t)t * plane, sd.probs + (size_t)t * plane, ny, nx,
                  sd.smooth_r, (float)sd.rd.N, sd.smooth_w.w, by * kBandRows,
-                 bx * kSmoothThreads, tile);
+                 bx * kSmoothThreads, tile, un);
     __syncthreads();  // the next tile rewrites `tile`
   }
 }
@@ -343,6 +378,10 @@ struct cap_plan {
   // last staged totals
   int64_t particles = 0, psteps = 0;
   int32_t tiles = 0;
+  // union stage: frame, horizon and caller's [ring][H][ny][nx] buffer (null: off)
+  cap_grid union_frame{};
+  int32_t union_H = 0;
+  float* union_dev = nullptr;
 };
 
 namespace capred {
@@ -526,6 +565,10 @@ static void split_tiles(const int32_t* units, int n, int P, int R, int C,
   }
 }
 
+static bool same_frame(const cap_grid& a, const cap_grid& b) {
+  return a.x0 == b.x0 && a.y0 == b.y0 && a.cell == b.cell && a.nx == b.nx && a.ny == b.ny;
+}
+
 // Fills ring entry e's host mirror from the active slots; returns its size.
 static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
   uint8_t* hostp = p->ring[e].host;
@@ -550,6 +593,7 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
     sd.rd.belief = hs.belief + (size_t)re * sd.bm.G * sd.bm.B;
     sd.n_cells = hs.n_cells;
     sd.reset = hs.reset ? 1 : 0;
+    sd.in_union = p->union_dev && sd.probs && same_frame(hs.grid, p->union_frame) ? 1 : 0;
     variant |= sd.rd.shift ? 1 : 0;
     hs.reset = false;
     sd.n_obs = hs.n_staged;
@@ -586,6 +630,17 @@ static size_t build_entry(cap_plan* p, int e, uint64_t seed, uint32_t cycle) {
   H->step_begin[n] = steps_total;
   H->smooth_begin[n] = sblocks;
   H->n_active = n;
+  if (p->union_dev) {
+    const int re = (int)(cycle % (uint32_t)p->cfg.ring);
+    const size_t cells = (size_t)p->union_H * p->union_frame.nx * p->union_frame.ny;
+    H->union_out = p->union_dev + (size_t)re * cells;
+    H->union_H = p->union_H;
+    H->union_nx = p->union_frame.nx;
+    H->union_ny = p->union_frame.ny;
+  } else {
+    H->union_out = nullptr;
+    H->union_H = H->union_nx = H->union_ny = 0;
+  }
   p->last_variant = variant;
   // tile kinds of the persistent launch
   {
@@ -920,9 +975,9 @@ extern "C" cap_status cap_plan_replay_rollout(cap_plan* p, void* stream, void* e
   if (p->last_run_entry < 0) return fail(CAP_E_INVALID, "no cycle has run on this plan");
   hipStream_t s = as_stream(stream);
   const Entry& en = p->ring[p->last_run_entry];
-  const int minus1 = -1;
+  const int replay = -2;  // every slot, union grid untouched
   hipLaunchKernelGGL(plan_zero_kernel, dim3(2048), dim3(256), 0, s, (const uint8_t*)en.dev,
-                     en.queues, minus1);
+                     en.queues, replay);
   if (ev_start) CAP_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(ev_start), s));
   cap_status st = launch_rollout(p, en, p->last_variant, s);
   if (st != CAP_OK) return st;
@@ -969,6 +1024,23 @@ extern "C" cap_status cap_plan_tile_split(const int32_t* units, int32_t n,
     if (units[i] < 0) return fail(CAP_E_INVALID, "units must be >= 0");
   split_tiles(units, n, particles_per_thread, resident_blocks, cus,
               reinterpret_cast<int32_t(*)[kTileKinds]>(counts));
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_plan_set_union(cap_plan* p, const cap_grid* frame, int32_t H,
+                                         float* union_dev) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  if (!union_dev) {
+    p->union_dev = nullptr;
+    p->union_H = 0;
+    return CAP_OK;
+  }
+  cap_status st = check_grid(frame);
+  if (st != CAP_OK) return st;
+  if (H < 1 || H > 4096) return fail(CAP_E_INVALID, "union H must be in [1, 4096]");
+  p->union_frame = *frame;
+  p->union_H = H;
+  p->union_dev = union_dev;
   return CAP_OK;
 }
 

@@ -47,11 +47,13 @@ inline size_t smooth_lds_bytes(int r) {
 // grid into the LDS tile (the 2r+1 shifted loads of a row share cache lines);
 // pass 2 blurs the tile along y and writes row-coalesced.  Every thread of the
 // block must call it (it contains a barrier); the caller separates two calls
-// that reuse `tile` with another barrier.
+// that reuse `tile` with another barrier.  un (nullable): that step's plane of
+// a union grid of the same frame, raised to each nonzero output by an integer
+// atomic max on the FP32 bits (exact for values >= 0).
 __device__ __forceinline__ void smooth_block(const uint32_t* __restrict__ c,
                                              float* __restrict__ o, int ny, int nx, int r,
                                              float Nf, const float* __restrict__ w, int y0,
-                                             int x0, float* tile) {
+                                             int x0, float* tile, float* un = nullptr) {
   const int x = x0 + (int)threadIdx.x;
   const int rows = kBandRows + 2 * r;
   for (int i = 0; i < rows; ++i) {
@@ -73,7 +75,11 @@ __device__ __forceinline__ void smooth_block(const uint32_t* __restrict__ c,
       float acc = 0.f;
       for (int d = -r; d <= r; ++d)
         acc = fmaf(w[d + r], tile[(j + r - d) * kSmoothThreads + threadIdx.x], acc);
-      o[(size_t)(y0 + j) * nx + x] = acc / Nf;
+      const float v = acc / Nf;
+      o[(size_t)(y0 + j) * nx + x] = v;
+      if (un && v > 0.f)
+        __hip_atomic_fetch_max(reinterpret_cast<uint32_t*>(un) + (size_t)(y0 + j) * nx + x,
+                               __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

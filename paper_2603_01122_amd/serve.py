@@ -68,6 +68,80 @@ class CycleRecord:
         return None if self.completed is None else self.completed - self.release
 
 
+class Admission:
+    """Host-side admission control of the serving loop (no device work, so it
+    is testable on its own).  A human waits in FIFO order until a slot is free
+    and the particle budget has room for its N; a request that does not fit
+    does not block later ones that do.  A departed human's slot is reused only
+    once every completion predicate handed to depart() reports done (the
+    cycles in flight that still read or write the slot's buffers)."""
+
+    def __init__(self, n_slots: int, budget: Optional[int] = None):
+        self.free: List[int] = list(range(n_slots))
+        self.retiring: List[Tuple[int, List]] = []
+        self.waiting: collections.deque = collections.deque()
+        self.budget = budget
+        self.in_use = 0
+        self.active: Dict[int, Tuple[int, int]] = {}   # hid -> (slot, N)
+
+    def submit(self, r) -> None:
+        self.waiting.append(r)
+
+    def depart(self, hid: int, busy: Sequence = ()) -> Optional[int]:
+        """Removes `hid` (active or waiting).  busy: completion predicates
+        (objects with .query()) of the in-flight work that uses its slot.
+        Returns the slot it held, or None if it was still waiting."""
+        if hid in self.active:
+            s, n = self.active.pop(hid)
+            self.in_use -= n
+            busy = list(busy)
+            if busy:
+                self.retiring.append((s, busy))
+            else:
+                self.free.append(s)
+            return s
+        self.waiting = collections.deque(r for r in self.waiting if r.hid != hid)
+        return None
+
+    def reclaim(self) -> None:
+        keep = []
+        for s, evs in self.retiring:
+            if all(e.query() for e in evs):
+                self.free.append(s)
+            else:
+                keep.append((s, evs))
+        self.retiring = keep
+
+    def admit(self) -> List[Tuple[int, object]]:
+        """Reclaims finished slots, then admits waiting requests in order while
+        slots and budget allow; returns [(slot, request)]."""
+        self.reclaim()
+        out, kept = [], collections.deque()
+        while self.waiting:
+            r = self.waiting.popleft()
+            fits = self.budget is None or self.in_use + r.N <= self.budget
+            if self.free and fits:
+                s = self.free.pop(0)
+                self.active[r.hid] = (s, r.N)
+                self.in_use += r.N
+                out.append((s, r))
+            else:
+                kept.append(r)
+        self.waiting = kept
+        return out
+
+
+def latency_summary(latencies: Sequence[float], period: float) -> dict:
+    """p50 / p99 / max latency (ms) and deadline misses (latency > period) of
+    completed cycles (seconds)."""
+    lat = np.asarray(latencies, np.float64)
+    return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+            "max_ms": round(float(lat.max()) * 1e3, 4), "cycles": int(lat.size),
+            "deadline_ms": round(period * 1e3, 3),
+            "deadline_misses": int(np.count_nonzero(lat > period))}
+
+
 class Server:
     def __init__(self, K: int, speed: float, dt: float, n_slots: int, max_H: int, max_nx: int,
                  max_ny: int, max_G: int, max_B: int, ring: int = 2, n_streams: int = 2,
@@ -75,7 +149,8 @@ class Server:
                  tuning: Optional[dict] = None, max_smooth_radius: int = 0, speeds=None,
                  stationary: Optional[Tuple[float, int]] = None,
                  goal_departure: Optional[float] = None, device="cuda",
-                 freeze_gc: bool = True, history: int = 1 << 16):
+                 freeze_gc: bool = True, history: int = 1 << 16,
+                 union: Optional[Tuple[Sequence, int]] = None, clock=time.perf_counter):
         """stationary = (eps, mask): a human whose newest observed step is shorter
         than eps metres is predicted with the allowed speeds `mask` only (Q = -inf
         for the others, Sec. IV-B) until it moves again.  goal_departure = r: a
@@ -83,7 +158,12 @@ class Server:
         from all of them gets a uniform belief before the next update (Sec. IV-B).
         The paper specifies neither detector; these are the simplest readings.
         freeze_gc: gc.freeze() once the server is built (see the module notes).
-        history: how many of the latest CycleRecords `records` keeps."""
+        history: how many of the latest CycleRecords `records` keeps.
+        union = (frame, H): every cycle also writes, inside its graph, the
+        point-wise maximum of the probabilities of the humans whose grid is
+        `frame` (the planner's single occupancy map of Sec. IV-B), read with
+        union_grid(cycle).  clock: the host clock of release and completion
+        times (seconds)."""
         tuning = tuning or {}
         self.plan = capred.Plan(K, speed, dt, n_slots, max_obs=1, ring=ring,
                                 max_smooth_radius=max_smooth_radius, speeds=speeds, **tuning)
@@ -102,15 +182,16 @@ class Server:
         self.pool_lb = torch.zeros((n_slots, max_G * max_B), dtype=torch.float64, device=device)
         self.pool_b = torch.zeros((n_slots, ring * max_G * max_B), dtype=torch.float64,
                                   device=device)
-        self.free: List[int] = list(range(n_slots))
-        # departed slots and the completion events of the cycles in flight that
-        # still use them; a slot returns to `free` once all have completed
-        self._retiring: List[Tuple[int, List[torch.cuda.Event]]] = []
+        self.pool_union = None
+        if union is not None:
+            frame, uH = union
+            self.pool_union = torch.zeros((ring, uH, int(frame[4]), int(frame[3])),
+                                          dtype=torch.float32, device=device)
+            self.plan.set_union(frame, uH, self.pool_union)
+        self.adm = Admission(n_slots, particle_budget)
+        self.clock = clock
         self.slot_of: Dict[int, int] = {}
         self.req: Dict[int, HumanRequest] = {}
-        self.waiting: collections.deque = collections.deque()
-        self.budget = particle_budget
-        self.in_use = 0
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         # The pools are filled on the caller's current stream; the serving streams
         # must not start before those fills (nor before any later host-driven
@@ -130,22 +211,21 @@ class Server:
         if H > self.max[0] or nx > self.max[1] or ny > self.max[2] or r.model.G > self.max[3] \
                 or r.model.B > self.max[4] or r.model.K != self.K:
             raise ValueError(f"human {r.hid} exceeds the slot capacity of this server")
-        self.waiting.append(r)
+        self.adm.submit(r)
+
+    @property
+    def waiting(self) -> collections.deque:
+        return self.adm.waiting
 
     def depart(self, hid: int):
         for d in (self._last_xy, self._at_goal, self._masked):
             d.pop(hid, None)
-        if hid in self.slot_of:
-            s = self.slot_of.pop(hid)
+        busy = [r.done_event for r in self._pending if hid in r.humans]
+        s = self.adm.depart(hid, busy)
+        if s is not None:
+            self.slot_of.pop(hid)
+            self.req.pop(hid)
             self.plan.retire(s)
-            self.in_use -= self.req.pop(hid).N
-            busy = [r.done_event for r in self._pending if hid in r.humans]
-            if busy:
-                self._retiring.append((s, busy))
-            else:
-                self.free.append(s)
-        else:
-            self.waiting = collections.deque(r for r in self.waiting if r.hid != hid)
 
     def _views(self, s: int, r: HumanRequest) -> capred.SlotBuffers:
         R, H, nx, ny = self.ring, r.H, int(r.grid[3]), int(r.grid[4])
@@ -158,36 +238,16 @@ class Server:
             self.pool_lb[s, :G * B].view(G, B),
             self.pool_b[s, :R * G * B].view(R, G, B))
 
-    def _reclaim(self):
-        """Returns departed slots whose in-flight cycles have all completed."""
-        keep = []
-        for s, evs in self._retiring:
-            if all(e.query() for e in evs):
-                self.free.append(s)
-            else:
-                keep.append((s, evs))
-        self._retiring = keep
-
     def _admit_waiting(self):
-        self._reclaim()
-        kept = collections.deque()
-        while self.waiting:
-            r = self.waiting.popleft()
-            fits = self.budget is None or self.in_use + r.N <= self.budget
-            if self.free and fits:
-                s = self.free.pop(0)
-                buf = self._views(s, r)
-                if r.log_belief is not None:
-                    buf.log_belief.copy_(torch.as_tensor(r.log_belief, dtype=torch.float64))
-                    self._after_current_stream()
-                self.plan.admit(s, r.hid, r.model, r.grid, r.N, r.H, r.last_xy, buf,
-                                reset_belief=r.log_belief is None, smooth=r.smooth)
-                self.slot_of[r.hid] = s
-                self.req[r.hid] = r
-                self.in_use += r.N
-            else:
-                kept.append(r)
-        self.waiting = kept
+        for s, r in self.adm.admit():
+            buf = self._views(s, r)
+            if r.log_belief is not None:
+                buf.log_belief.copy_(torch.as_tensor(r.log_belief, dtype=torch.float64))
+                self._after_current_stream()
+            self.plan.admit(s, r.hid, r.model, r.grid, r.N, r.H, r.last_xy, buf,
+                            reset_belief=r.log_belief is None, smooth=r.smooth)
+            self.slot_of[r.hid] = s
+            self.req[r.hid] = r
 
     # ----------------------------------------------------------- cycles
     def step(self, observations: Dict[int, Sequence[float]], release: Optional[float] = None,
@@ -211,7 +271,7 @@ class Server:
             else:
                 self.plan.run(self.seed, self.cycle)
             ev.record(stream)
-        rec = CycleRecord(self.cycle, time.perf_counter() if release is None else release, ev,
+        rec = CycleRecord(self.cycle, self.clock() if release is None else release, ev,
                           sorted(self.slot_of), sum(self.req[h].N * self.req[h].H
                                                     for h in self.slot_of))
         self.records.append(rec)
@@ -247,7 +307,7 @@ class Server:
 
     def poll(self) -> int:
         """Marks finished cycles (non-blocking); returns how many are still pending."""
-        now = time.perf_counter()
+        now = self.clock()
         while self._pending and self._pending[0].done_event.query():
             self._pending.popleft().completed = now
         return len(self._pending)
@@ -265,6 +325,10 @@ class Server:
         e = cycle % self.ring
         return (b.counts[e], None if b.probs is None else b.probs[e], b.offgrid[e], b.belief[e])
 
+    def union_grid(self, cycle: int) -> torch.Tensor:
+        """[H, ny, nx] union of `cycle` (valid until its ring entry is reused)."""
+        return self.pool_union[cycle % self.ring]
+
     def log_belief(self, hid: int) -> torch.Tensor:
         """`hid`'s log posterior [G, B] after the newest cycle that has run
         (read it once that cycle is complete, e.g. after drain())."""
@@ -276,24 +340,29 @@ class Server:
         self.plan.close()
 
 
-def run_paced(server: Server, obs_fn, n_cycles: int, rate_hz: float = 125.0,
-              progress=None) -> np.ndarray:
+def run_paced(server, obs_fn, n_cycles: int, rate_hz: float = 125.0, progress=None,
+              before_step=None, clock=time.perf_counter, sleep=time.sleep) -> np.ndarray:
     """Fixed-rate loop: cycle c is released at t0 + c/rate; between ticks the
     host polls the completion events, every ~50 us while a cycle is in flight
     (so that a completion is seen within about that) and every millisecond
-    otherwise.  obs_fn(c) -> {hid: xy}.  Returns latencies (s)."""
+    otherwise.  before_step(c) (optional) runs after the release tick, before
+    the cycle is launched (arrivals and departures: their host work counts in
+    that cycle's latency).  obs_fn(c) -> {hid: xy}.  Returns latencies (s);
+    the server must stamp completions with the same clock."""
     period = 1.0 / rate_hz
-    t0 = time.perf_counter() + 2 * period
+    t0 = clock() + 2 * period
     recs = []
     for c in range(n_cycles):
         tick = t0 + c * period
         while True:
             pending = server.poll()
-            now = time.perf_counter()
+            now = clock()
             if now >= tick:
                 break
             if tick - now > 200e-6:
-                time.sleep(min(tick - now - 150e-6, 50e-6 if pending else 1e-3))
+                sleep(min(tick - now - 150e-6, 50e-6 if pending else 1e-3))
+        if before_step is not None:
+            before_step(c)
         recs.append(server.step(obs_fn(c), release=tick))
         if progress and (c + 1) % progress[0] == 0:
             progress[1](c + 1)

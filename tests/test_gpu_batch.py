@@ -306,6 +306,56 @@ def test_long_run_all_humans_parity(orc, cap):
     srv.close()
 
 
+def test_union_in_cycle(orc, cap):
+    """The union stage inside the cycle (Sec. IV-B point-wise maximum): every
+    cycle's union grid equals the oracle's maximum over the probability grids of
+    the humans that share the union's frame (steps beyond a human's horizon
+    count as 0), excluding a human on another grid; one member has smoothed
+    probabilities; batched and per-human launches give the same bits, and a
+    replay of the rollout leaves the union alone."""
+    humans = small_scene(n=5, N_div=8, H=20)
+    humans[1].H = 14
+    humans[3].grid = (humans[3].grid[0], humans[3].grid[1], humans[3].grid[2],
+                      humans[3].grid[3], 200)          # another frame: not in the union
+    frame, uH = humans[0].grid, 20
+    tr = tracks_for(orc, humans, 5)
+    sm = {humans[2].hid: (1.0, 2)}
+    note("union of 4 of 5 humans inside the cycle, batched and plain, 3 cycles")
+    from paper_2603_01122_amd.serve import Server
+    h0 = humans[0]
+    mk = lambda: Server(h0.K, h0.speed, h0.dt, len(humans), 20, 256, 256, max(h.G for h in humans),
+                        9, max_smooth_radius=2, union=(frame, uH))
+    A, Bp = mk(), mk()
+    for h in humans:
+        A.submit(request(cap, h, tr[h.hid][0], smooth=sm.get(h.hid)))
+        Bp.submit(request(cap, h, tr[h.hid][0], smooth=sm.get(h.hid)))
+    for c in range(3):
+        obs = {h.hid: tr[h.hid][c + 1] for h in humans}
+        A.step(obs)
+        Bp.step(obs, plain=True)
+        A.drain()
+        Bp.drain()
+        torch.cuda.synchronize()
+        members = []
+        for h in humans:
+            if h.hid == humans[3].hid:
+                continue
+            probs = snapshot(A, h.hid, c)[1]
+            padded = np.zeros((uH,) + probs.shape[1:], np.float32)
+            padded[:h.H] = probs
+            members.append(padded)
+        ref = orc.union_max(members)
+        got = A.union_grid(c).cpu().numpy()
+        assert np.array_equal(got, ref), c
+        assert np.array_equal(Bp.union_grid(c).cpu().numpy(), ref), c
+        assert np.count_nonzero(ref[humans[1].H:]) > 0
+    A.plan.replay_rollout()
+    torch.cuda.synchronize()
+    assert np.array_equal(A.union_grid(2).cpu().numpy(), ref)
+    A.close()
+    Bp.close()
+
+
 def test_continuous_batching_invariance(orc, cap):
     humans = small_scene(n=5, N_div=8, H=25)
     tr = tracks_for(orc, humans, 12)
