@@ -129,10 +129,20 @@ def make_server(capred, humans, tuning, tracks):
     return srv
 
 
-def cpu_baseline(scene, max_seconds, min_seconds=10.0):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, max_seconds, n_cycles=10):
     """The FP64 oracle on whole serving cycles (belief update with the newest
     observation + Alg. 1 for all humans), on every host core this process may
-    use, for at least min_seconds (whole cycles, at most max_seconds).  Its
+    use: n_cycles whole cycles, or fewer if max_seconds run out first.  Its
     observations come from its own track simulator."""
     import numpy as np
     import oracle
@@ -164,7 +174,7 @@ def cpu_baseline(scene, max_seconds, min_seconds=10.0):
         if time.perf_counter() - t0 > max_seconds:
             break
         cycles += 1
-        if time.perf_counter() - t0 >= min_seconds:
+        if cycles >= n_cycles:
             break
     dt = time.perf_counter() - t0
     n_h = len(scene.humans)
@@ -172,7 +182,8 @@ def cpu_baseline(scene, max_seconds, min_seconds=10.0):
               f"({steps} particle-steps)" if humans_done == cycles * n_h else
               f"{humans_done} human-cycles of the {n_h}-human workload ({steps} particle-steps)")
     return {"value": steps / dt, "unit": "particle-steps/s", "cores": threads,
-            "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
+            "kind": "oracle", "sample": sample, "seconds": round(dt, 3),
+            "cpu_model": cpu_model()}
 
 
 def profiled_traffic(best):
@@ -264,10 +275,29 @@ def loglik_timing(capred, torch, np, scenes, reps=20):
             tb.append(ev[1].elapsed_time(ev[2]))
     terms = n * ts.T * goals.shape[0] * log_beta.numel()
     fwd, bwd = float(np.median(tf)), float(np.median(tb))
+    # goal / per-track beta fit from perturbed goals (300 Adam steps)
+    from paper_2603_01122_amd.fit import fit_goals_beta
+    r = np.random.default_rng(1)
+    goals0 = torch.tensor((ts.goals + r.normal(scale=0.4, size=ts.goals.shape)).astype(np.float32),
+                          device="cuda")
+    lb0 = torch.zeros((n, 1), dtype=torch.float32, device="cuda")
+    fit_goals_beta(ts.K, ts.speed, ts.dt, tracks, lengths, goals0, lb0, iters=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = fit_goals_beta(ts.K, ts.speed, ts.dt, tracks, lengths, goals0, lb0, iters=300)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    err = np.linalg.norm(res.goals.cpu().numpy().astype(np.float64) - ts.goals, axis=1)
     return {"tracks": n, "steps": ts.T, "goals": int(goals.shape[0]), "beta": int(log_beta.numel()),
             "K": ts.K, "forward_ms": round(fwd, 4), "backward_ms": round(bwd, 4),
             "policy_terms_per_s_forward": float(f"{terms / (fwd * 1e-3):.4e}"),
-            "policy_terms_per_s_backward": float(f"{terms / (bwd * 1e-3):.4e}")}
+            "policy_terms_per_s_backward": float(f"{terms / (bwd * 1e-3):.4e}"),
+            "fit": {"adam_steps": 300, "seconds": round(fit_s, 4),
+                    "ms_per_step": round(fit_s / 300 * 1e3, 4),
+                    "start_goal_error_m": 0.4,
+                    "max_goal_error_m": round(float(err.max()), 5),
+                    "objective_first_last": [round(res.objective[0], 5),
+                                             round(res.objective[-1], 5)]}}
 
 
 def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
@@ -334,6 +364,96 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
                          "resources": resources}}
 
 
+def churn_paced(capred, torch, np, scenes, tuning, n_cycles, rate):
+    """Continuous batching under churn: the 125 Hz loop over a seeded schedule
+    of arrivals and departures (scenes.config3_churn: 16 humans at first, then
+    Poisson arrivals with stays of 200-1400 cycles, about 16-18 present).  The
+    server has 16 slots and a particle budget equal to the 16-human workload's
+    total N, so arrivals wait for a slot and for budget and join at cycle
+    boundaries; arrivals and departures are handled after each release tick,
+    inside that cycle's latency.  Every present human walks one simulated step
+    per cycle (waiting ones too: they join from where they are)."""
+    import dataclasses
+    from paper_2603_01122_amd.serve import HumanRequest, Server, latency_summary, run_paced
+    visits = scenes.config3_churn(n_cycles)
+    T = max(v.depart - v.arrive for v in visits) + 2
+    walkers = [dataclasses.replace(v.human, hid=v.hid) for v in visits]
+    sims = simulate(capred, torch, np, walkers, T)
+    budget = sum(h.N for h in scenes.config3().humans)
+    h0 = walkers[0]
+    srv = Server(h0.K, h0.speed, h0.dt, 16, 100, 256, 256, 6, 9, particle_budget=budget,
+                 tuning=tuning)
+    arrive, depart = {}, {}
+    for v in visits:
+        arrive.setdefault(v.arrive, []).append(v)
+        depart.setdefault(v.depart, []).append(v)
+    present = {}
+
+    def before(c):
+        for v in depart.get(c, []):
+            srv.depart(v.hid)
+            present.pop(v.hid, None)
+        for v in arrive.get(c, []):
+            srv.submit(HumanRequest(v.hid, capred.model_of(v.human), v.human.grid, v.human.N,
+                                    v.human.H, sims[v.hid][0]))
+            present[v.hid] = v
+        for r in srv.waiting:
+            r.last_xy = sims[r.hid][c - present[r.hid].arrive]
+
+    def obs(c):
+        return {hid: sims[hid][c - v.arrive + 1] for hid, v in present.items()}
+
+    try:
+        lat = run_paced(srv, obs, n_cycles, rate, before_step=before,
+                        progress=(2000, lambda k: log(f"  churn {k} cycles")))
+        recs = list(srv.records)[-n_cycles:]
+    finally:
+        srv.close()
+    first = {}
+    for r in recs:
+        for hid in r.humans:
+            first.setdefault(hid, r.cycle)
+    waits = [first[v.hid] - v.arrive for v in visits if v.hid in first]
+    out = latency_summary(lat, 1.0 / rate)
+    out.update({"rate_hz": rate, "visits": len(visits), "admitted": len(first),
+                "mean_humans": round(float(np.mean([len(r.humans) for r in recs])), 2),
+                "mean_particle_steps_per_cycle": float(f"{np.mean([r.particle_steps for r in recs]):.4e}"),
+                "max_wait_cycles": int(max(waits)), "mean_wait_cycles": round(float(np.mean(waits)), 2),
+                "slots": 16, "particle_budget": budget})
+    return out
+
+
+def union_in_cycle(capred, torch, np, humans, tuning, tracks, cycles, start):
+    """Back-to-back cycles of the 16-human workload with the union stage on
+    (the point-wise maximum of the 16 humans' probabilities, which share one
+    frame, written inside each cycle's graph), against the same cycles without it."""
+    from paper_2603_01122_amd.serve import HumanRequest, Server
+    h0 = humans[0]
+    out = {}
+    for name, union in (("without", None), ("with", (h0.grid, h0.H))):
+        srv = Server(h0.K, h0.speed, h0.dt, len(humans), h0.H, 256, 256, 6, 9, tuning=tuning,
+                     union=union)
+        try:
+            for h in humans:
+                srv.submit(HumanRequest(h.hid, capred.model_of(h), h.grid, h.N, h.H,
+                                        tracks[h.hid][start]))
+            for c in range(start, start + 10):
+                srv.step({h.hid: tracks[h.hid][c + 1] for h in humans})
+            srv.drain()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in range(start + 10, start + 10 + cycles):
+                srv.step({h.hid: tracks[h.hid][c + 1] for h in humans})
+            torch.cuda.synchronize()
+            out[name] = (time.perf_counter() - t0) / cycles
+        finally:
+            srv.close()
+    return {"cycle_ms_without_union": round(out["without"] * 1e3, 4),
+            "cycle_ms_with_union": round(out["with"] * 1e3, 4),
+            "union_in_cycle_ms": round((out["with"] - out["without"]) * 1e3, 4),
+            "cycles": cycles}
+
+
 def tab1_latency(capred, torch, np, calls=50):
     """One prediction at the shape of the paper's Tab. 1 (1 human, n = 8192,
     50 x 50 grid at 0.1 m, 5 beta, 10 goals, 96 controls = 6 speeds x 16
@@ -384,8 +504,11 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=30)
     ap.add_argument("--paced-cycles", type=int, default=10000)
     ap.add_argument("--rate", type=float, default=125.0)
+    ap.add_argument("--churn-cycles", type=int, default=10000,
+                    help="paced cycles under the arrival/departure schedule (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--cpu-seconds", type=float, default=40.0,
+                    help="cap on the oracle's 10 whole cycles")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--retune", action="store_true",
                     help="autotune even where the package's table holds this device and workload")
@@ -415,7 +538,8 @@ def main():
     humans = scene.humans
     psteps = scene.particle_steps
     n_tune = 2 * 9 * 10
-    T = args.warmup + args.steps + args.plain_steps + args.paced_cycles + n_tune + 64
+    T = (args.warmup + args.steps + args.plain_steps + args.paced_cycles + n_tune + 64 +
+         2 * (10 + args.steps))
     log(f"simulating {len(humans)} tracks x {T} steps")
     tracks = simulate(capred, torch, np, humans, T)
 
@@ -507,12 +631,21 @@ def main():
         c += args.paced_cycles
     srv.drain()
     mppi = mppi_timing(capred, torch, np, srv, humans, c - 1)
+    srv.close()
+    mppi.update(union_in_cycle(capred, torch, np, humans, best, tracks, args.steps, c))
+    log(f"union inside the cycle: {mppi['cycle_ms_with_union']} ms/cycle with, "
+        f"{mppi['cycle_ms_without_union']} without")
+    churn = None
+    if args.churn_cycles > 0:
+        log(f"paced loop under churn: {args.churn_cycles} cycles at {args.rate} Hz")
+        churn = churn_paced(capred, torch, np, scenes, best, args.churn_cycles, args.rate)
+        log(f"  churn: p50 {churn['p50_ms']} ms, p99 {churn['p99_ms']} ms, misses "
+            f"{churn['deadline_misses']}, {churn['admitted']} of {churn['visits']} visits admitted")
     diff = loglik_timing(capred, torch, np, scenes)
     log(f"log-likelihood, 1024 tracks x 200 steps x 8 goals x 9 beta: forward "
         f"{diff['forward_ms']} ms, backward {diff['backward_ms']} ms")
     log(f"union of 16 grids {mppi['union_ms']} ms ({mppi['union_GBps']} GB/s), "
         f"MPPI step {mppi['mppi_ms']} ms")
-    srv.close()
 
     # ---------------------------------------------------------- plain per-human launches
     psrv = make_server(capred, humans, best_plain, tracks)
@@ -545,18 +678,18 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, whole cycles for at least 10 s)")
+        log(f"cpu baseline (oracle, 10 whole cycles) on {cpu_model()}")
         cpu = cpu_baseline(scene, args.cpu_seconds)
 
     latency = None
     if lat is not None:
-        period = 1.0 / args.rate
-        latency = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
-                   "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
-                   "max_ms": round(float(lat.max()) * 1e3, 4),
-                   "cycles": int(lat.size), "rate_hz": args.rate,
-                   "deadline_ms": round(period * 1e3, 3),
-                   "deadline_misses": int(np.count_nonzero(lat > period))}
+        from paper_2603_01122_amd.serve import latency_summary
+        latency = latency_summary(lat, 1.0 / args.rate)
+        latency["rate_hz"] = args.rate
+        latency["mix"] = "static: the same 16 humans every cycle"
+    if churn is not None:
+        latency = latency or {}
+        latency["churn"] = churn
     result = {
         "metric": METRIC,
         "value": float(f"{value:.6e}"),

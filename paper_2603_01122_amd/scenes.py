@@ -109,6 +109,39 @@ def config3(n_humans: int = 16, n_obs: int = 20) -> Scene:
     return Scene("config3", humans)
 
 
+@dataclasses.dataclass
+class Visit:
+    """One human's stay in a continuous-batching run."""
+    hid: int                      # fresh stable id of this visit (keys its random streams)
+    human: Human                  # identity: N, goals, start, true beta and goal
+    arrive: int                   # cycle at which the request is submitted
+    depart: int                   # first cycle without it
+
+
+def config3_churn(n_cycles: int = 10000, n_identities: int = 48, mean_dwell: int = 800,
+                  seed: int = 33) -> List[Visit]:
+    """Arrivals and departures for the 16-human serving workload: the 16 humans
+    of config3 are present at cycle 0; later visitors arrive as a Poisson
+    process of rate 16 / mean_dwell per cycle (so that about 16 are present on
+    average), with identities drawn uniformly from config3(n_identities) (the
+    first 16 are config3's humans); every stay lasts U[mean_dwell / 4,
+    7 mean_dwell / 4] cycles.  Visit ids are 1000 + visit index."""
+    ids = config3(n_identities).humans
+    r = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = max(1, mean_dwell // 4), max(2, 7 * mean_dwell // 4)
+    visits = []
+    for h in ids[:16]:
+        visits.append(Visit(1000 + len(visits), h, 0, int(r.integers(lo, hi + 1))))
+    rate = 16.0 / mean_dwell
+    t = float(r.exponential(1.0 / rate))
+    while t < n_cycles:
+        c = int(t)
+        h = ids[int(r.integers(0, n_identities))]
+        visits.append(Visit(1000 + len(visits), h, c, c + int(r.integers(lo, hi + 1))))
+        t += float(r.exponential(1.0 / rate))
+    return visits
+
+
 def config5(n_humans: int = 64, n_obs: int = 20) -> Scene:
     """64 humans x N=2^20, 6 goals each, 9 beta, K=32, v=1.2, dt=0.01, H=200,
     512x512 grids at 0.02 m (arena = grid = 10.24 m)."""

@@ -5,14 +5,13 @@
   oracle (the oracle computes any track on its own);
 * adjoint: the full-size gradients (sums over all tracks) within 1e-5
   norm-wise of the oracle's analytic gradient;
-* fit: gradient ascent through LogLik.apply on the marginal likelihood
-  J = sum_n log sum_g exp(LL[n, g]) / G (per-track log beta) recovers the 8
-  true goals to a few centimetres; on a subset, the GPU-driven and the
-  oracle-driven fits from the same start with the same optimiser agree to
-  1e-4 m.  The paper gives no tolerance for the recovery itself (parity
+* fit (the package's fit_goals_beta): Adam ascent through LogLik.apply on
+  the marginal likelihood J = sum_n log sum_g exp(LL[n, g]) / G (per-track log
+  beta) recovers the 8 true goals to a few centimetres; on a subset, the
+  GPU-driven and the oracle-driven fits from the same start with the same
+  optimiser agree to 1e-4 m.  The paper gives no tolerance for the recovery itself (parity
   unpinned beyond this agreement).
 """
-import math
 import sys
 
 import numpy as np
@@ -74,24 +73,12 @@ def test_full_size_forward_sampled_and_backward(orc, cap, tracks):
     assert np.linalg.norm(db - db_o) <= 1e-5 * np.linalg.norm(db_o)
 
 
-def _objective_torch(LL, G):
-    # marginal over goals with a uniform goal prior, per-track beta (B = 1)
-    return (torch.logsumexp(LL[:, 0, :], dim=1) - math.log(G)).sum()
-
-
 def _fit_gpu(cap, ts, pos, lengths, goals0, lb0, iters, lr):
+    from paper_2603_01122_amd.fit import fit_goals_beta
     t = lambda a: torch.tensor(a, device="cuda")
-    g = t(goals0).requires_grad_(True)
-    b = t(lb0).requires_grad_(True)
-    P, L = t(pos), t(lengths)
-    opt = torch.optim.Adam([g, b], lr=lr)
-    for _ in range(iters):
-        opt.zero_grad()
-        LL = cap.LogLik.apply(g, b, P, L, ts.K, ts.speed, ts.dt)
-        loss = -_objective_torch(LL, g.shape[0]) / pos.shape[0]
-        loss.backward()
-        opt.step()
-    return g.detach().cpu().numpy().astype(np.float64), b.detach().cpu().numpy()
+    res = fit_goals_beta(ts.K, ts.speed, ts.dt, t(pos), t(lengths), t(goals0), t(lb0), iters, lr)
+    assert res.objective[-1] > res.objective[0]
+    return res.goals.cpu().numpy().astype(np.float64), res.log_beta.cpu().numpy()
 
 
 def _fit_oracle(orc, ts, pos, lengths, goals0, lb0, iters, lr):
