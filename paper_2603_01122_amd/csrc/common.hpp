@@ -100,8 +100,12 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 }
 
 // u = (2 (w >> 9) + 1) 2^-24: 24 significant bits, exact in FP32 and FP64.
+// In FP32 as two instructions: one funnel shift places w >> 9 in the mantissa
+// of 1.0 (x = 1 + (w >> 9) 2^-23), then x - (1 - 2^-24), exact by Sterbenz's
+// lemma (x and 1 - 2^-24 are within a factor of two).
 __device__ __forceinline__ float uniform24f(uint32_t w) {
-  return (float)((w >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
+  const uint32_t x = __builtin_amdgcn_alignbit(0x7Fu, w, 9u);  // 0x3F800000 | (w >> 9)
+  return __uint_as_float(x) - 0x1.fffffep-1f;
 }
 __device__ __forceinline__ double uniform24d(uint32_t w) {
   return (double)((w >> 9) * 2u + 1u) * 5.9604644775390625e-8;
@@ -227,8 +231,10 @@ __device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float 
 #pragma unroll
       for (int k = 0; k < KT; ++k) C[k] -= m;
     }
+    acc = fast_exp2(C[0]);
+    C[0] = acc;
 #pragma unroll
-    for (int k = 0; k < KT; ++k) {
+    for (int k = 1; k < KT; ++k) {
       acc += fast_exp2(C[k]);
       C[k] = acc;
     }

@@ -173,10 +173,15 @@ __device__ __forceinline__ void rollout_tile_body(const RolloutDesc& d, int64_t 
   for (int t = 1; t <= d.H; ++t, m3 = (m3 == 2 ? 0 : m3 + 1)) {
     const int s = (t - 1) & 3;
     if (s == 0) {
+      // The round keys (key + r * Weyl constant) are derived from the seed here,
+      // by scalar adds in every block, rather than held across the loop: kept,
+      // they would pin 20 scalar registers that the step's other uniform values
+      // need (the overflow goes to vector-register lanes, one VALU access each).
+      uint32_t klo = seed_lo, khi = seed_hi;
+      asm volatile("" : "+s"(klo), "+s"(khi));
 #pragma unroll
       for (int p = 0; p < P; ++p)
-        rw[p] = philox10((uint32_t)idx[p], (uint32_t)((t - 1) >> 2), d.human, c3_head, seed_lo,
-                         seed_hi);
+        rw[p] = philox10((uint32_t)idx[p], (uint32_t)((t - 1) >> 2), d.human, c3_head, klo, khi);
     }
     const Window wd = step_window(d, t);
     // two 16-bit counters per LDS word (a tile never holds 65536 particles);
@@ -218,14 +223,18 @@ __device__ __forceinline__ void rollout_tile_body(const RolloutDesc& d, int64_t 
       if (act[p]) {
         if (d.trace_k) as_global(d.trace_k)[(size_t)idx[p] * d.H + (t - 1)] = (uint8_t)k;
         const int cx = X[p] >> kLatticeShift, cy = Y[p] >> kLatticeShift;
-        if ((unsigned)cx < (unsigned)d.nx && (unsigned)cy < (unsigned)d.ny) {
+        if (lds_mode) {
+          // the particle's cell lies in the unclipped reach window, so it is on
+          // the grid exactly when it lies in the clipped window
           const unsigned lx = (unsigned)(cx - wd.x0), ly = (unsigned)(cy - wd.y0);
-          if (lds_mode && lx < (unsigned)wd.w && ly < (unsigned)wd.h) {
-            widx = ly * half_w + (lx >> 1);
+          if (lx < (unsigned)wd.w && ly < (unsigned)wd.h) {
+            widx = __umul24(ly, (unsigned)half_w) + (lx >> 1);  // both below 2^24
             fresh = atomicAdd(buf + widx, 1u << ((lx & 1u) << 4)) == 0u;
           } else {
-            global_add(grid_t + (size_t)cy * d.nx + cx, 1u);
+            off = true;
           }
+        } else if ((unsigned)cx < (unsigned)d.nx && (unsigned)cy < (unsigned)d.ny) {
+          global_add(grid_t + (size_t)cy * d.nx + cx, 1u);
         } else {
           off = true;
         }
@@ -241,13 +250,25 @@ __device__ __forceinline__ void rollout_tile_body(const RolloutDesc& d, int64_t 
     __syncthreads();
     // ---- flush the touched words of step t's window, clear them
     if (lds_mode) {
+      // Word w of the window is row ry = floor(w / half_w), cells 2 rx and 2 rx + 1
+      // with rx = w - ry half_w.  ry = trunc((w + 1/2) * fl(1/half_w)) exactly:
+      // (w + 1/2) / half_w lies at least 1/(2 half_w) from an integer, while the
+      // two roundings (reciprocal within 1 ulp, product) move it by at most
+      // 2^-22 (w + 1/2) / half_w <= 2^-22 * 65536 / half_w, since w < 2^16.
+      const float rhw = fast_rcp((float)half_w), hrhw = 0.5f * rhw;
+      // byte offset of the window's first cell within the step's plane (< 2^30)
+      const uint32_t base4 = 4u * ((uint32_t)wd.y0 * (uint32_t)d.nx + (uint32_t)wd.x0);
+      const uint32_t nx4 = 4u * (uint32_t)d.nx;
+      char* gbase = reinterpret_cast<char*>(grid_t);
       const uint32_t nt = sh.ntouch[m3];
       for (uint32_t i = tid; i < nt; i += nthr) {
         const uint32_t w = list[i];
         const uint32_t v = buf[w];
         buf[w] = 0u;
-        const uint32_t ry = w / (uint32_t)half_w, rx = 2u * (w - ry * (uint32_t)half_w);
-        uint32_t* g = grid_t + (size_t)(wd.y0 + ry) * d.nx + wd.x0 + rx;
+        const uint32_t ry = (uint32_t)fmaf((float)w, rhw, hrhw);
+        const uint32_t rx = w - __umul24(ry, (uint32_t)half_w);
+        const uint32_t off4 = __umul24(ry, nx4) + base4 + (rx << 3);
+        uint32_t* g = reinterpret_cast<uint32_t*>(gbase + off4);
         const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
         if (lo) global_add(g, lo);
         if (hi) global_add(g + 1, hi);
