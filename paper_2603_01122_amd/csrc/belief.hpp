@@ -8,11 +8,11 @@
 namespace capred {
 
 constexpr int kBeliefThreads = 256;
-constexpr int kBeliefChunk = 2;   // observed transitions staged in LDS at a time (8 KiB: the
-                                  // update fits beside the rollout blocks of a busy CU)
+constexpr int kDeltaSlots = 1024;  // Delta of one transition for a chunk of goals x all controls
+                                   // (8 KiB: the update fits beside the rollout blocks of a busy CU)
 
 struct BeliefShared {
-  double ell[kBeliefChunk * CAP_MAX_J];
+  double dl[kDeltaSlots];
   double red[kBeliefThreads / 64];
 };
 
@@ -20,7 +20,7 @@ struct BeliefShared {
 // heading k* = argmax_k <dz, (cos, sin)theta_k> with the lowest k on ties, then
 // the speed whose step v_s dt is nearest to that projection (lowest s on
 // ties); returns u* = s* K + k*, or -1 when the displacement is below 1e-9 m.
-__host__ __device__ __forceinline__ int recover_control(const BeliefModel& m, float dx, float dy) {
+__device__ __forceinline__ int recover_control(const BeliefModel& m, float dx, float dy) {
   if (fmaf(dx, dx, dy * dy) < 1e-18f) return -1;
   int ks = 0;
   float best = -INFINITY;
@@ -46,7 +46,7 @@ __host__ __device__ __forceinline__ int recover_control(const BeliefModel& m, fl
 // log pi(u* | z; beta_b, g) for every b over the U controls in plain FP32 (the
 // trajectory log-likelihood's terms: its bar is relative to |LL|, a sum of
 // hundreds of terms, so FP32 logits meet it; the posterior update uses the
-// compensated policy_term_one below).
+// compensated policy_delta and policy_term_from below).
 // Delta_u = |a + s_u| - |a| with a = z - g carried as an unevaluated sum
 // (hi + lo, exact subtraction), from the cancellation-free quotient
 // (2 a.s_u + |s_u|^2) / (|a + s_u| + |a|); then l_u = -beta Delta_u and
@@ -91,34 +91,45 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
   }
 }
 
-// log pi(u* | z; beta, g) of the posterior update, for one beta.  The update
-// multiplies up to thousands of these terms into a posterior whose log must
-// stay within 1e-5 of the exact one, and a term's rounding error grows with
-// beta |s| (about 15 at beta = 100 and a 0.15 m step): plain FP32 logits err
-// by a few 1e-6 per transition.  So the logits are evaluated in compensated
-// FP32 (hi + lo pairs, about 48 bits): a = z - g exactly, |a|^2,
-// n_u = 2 a.s_u + |s_u|^2 and Delta_u = n_u / (|a + s_u| + |a|) (the
-// cancellation-free difference of the two distances), l_u = -beta Delta_u;
-// each l_u is rounded once to FP64, where the log-sum-exp over the controls
-// runs (single pass with a running maximum).  log pi = (l_{u*} - max l) -
-// log sum exp(l - max l).  Error per term: a few 1e-13 of beta |s| plus the
-// FP64 exponentials', against 1e-5 over the whole history.
-__host__ __device__ __forceinline__ double policy_term_one(const BeliefModel& m, float zx, float zy, int ks,
-                                                  float gx, float gy, float beta) {
-  if (ks < 0) return 0.0;
-  const dfl ax = two_sum(zx, -gx), ay = two_sum(zy, -gy);
-  const dfl D2 = df_add(df_mul(ax, ax), df_mul(ay, ay));
-  const dfl D = df_sqrt(D2);
+// Delta_u = |a + s_u| - |a| for a = z - g, the distance change of control u
+// that the policy's logits -beta Delta_u are built from (the shift-invariant
+// form of beta Q).  The posterior multiplies up to thousands of these terms
+// into a log that must stay within 1e-5 of the exact one, and a logit's
+// rounding error scales with beta |s| (about 15 at beta = 100 and a 0.15 m
+// step): plain FP32 Delta errs by a few 1e-6 per transition.  So Delta is
+// evaluated in compensated FP32 (hi + lo pairs, about 46 bits): a = z - g
+// exactly, |a|^2, n_u = 2 a.s_u + |s_u|^2 and the cancellation-free quotient
+// n_u / (|a + s_u| + |a|), rounded once to FP64, where the rest of the term
+// (the product with beta and the log-sum-exp over the controls) runs.
+struct GoalOffset {
+  dfl ax, ay, D2, D;
+};
+
+__device__ __forceinline__ GoalOffset goal_offset(float zx, float zy, float gx, float gy) {
+  GoalOffset o;
+  o.ax = two_sum(zx, -gx);
+  o.ay = two_sum(zy, -gy);
+  o.D2 = df_add(df_mul(o.ax, o.ax), df_mul(o.ay, o.ay));
+  o.D = df_sqrt(o.D2);
+  return o;
+}
+
+__device__ __forceinline__ double policy_delta(const GoalOffset& o, float sx, float sy) {
+  const dfl s2 = df_add(two_prod(sx, sx), two_prod(sy, sy));
+  const dfl dot = df_add(df_mul_f(o.ax, sx), df_mul_f(o.ay, sy));
+  const dfl n = df_add(dfl{2.f * dot.hi, 2.f * dot.lo}, s2);
+  const dfl d = df_sqrt(df_add(o.D2, n));
+  return df_to_double(df_div(n, df_add(d, o.D)));
+}
+
+// log pi(u* | z; beta, g) from the U values -Delta_u: l_u = -beta Delta_u and
+// log pi = (l_{u*} - max l) - log sum exp(l - max l), FP64, one pass with a
+// running maximum.
+__device__ __forceinline__ double policy_term_from(const double* dl, int U, int ks, double beta) {
   double mx = -INFINITY, s = 0.0, lks = 0.0;
-  for (int k = 0; k < m.U; ++k) {
-    const float sx = m.sx[k], sy = m.sy[k];
-    const dfl s2 = df_add(two_prod(sx, sx), two_prod(sy, sy));
-    const dfl dot = df_add(df_mul_f(ax, sx), df_mul_f(ay, sy));
-    const dfl n = df_add(dfl{2.f * dot.hi, 2.f * dot.lo}, s2);
-    const dfl d = df_sqrt(df_add(D2, n));
-    const dfl delta = df_div(n, df_add(d, D));
-    const double l = -df_to_double(df_mul_f(delta, beta));
-    if (k == ks) lks = l;
+  for (int u = 0; u < U; ++u) {
+    const double l = -beta * dl[u];
+    if (u == ks) lks = l;
     if (l > mx) {
       s = s * exp(mx - l) + 1.0;
       mx = l;
@@ -145,34 +156,41 @@ __device__ __forceinline__ double block_reduce(double v, bool is_max, double* re
 }
 
 // One human's update: log_belief[j] += sum_t ell_t(j), renormalised by one
-// FP64 log-sum-exp.  All sums run in a fixed order (bitwise reproducible).
+// FP64 log-sum-exp.  Per transition and chunk of goals, the threads first
+// evaluate every (goal, control) Delta once into LDS, then every (goal, beta)
+// term from them; thread tid owns pairs j = tid + r blockDim.x and adds their
+// terms in transition order, so all sums run in a fixed order (bitwise
+// reproducible).
 __device__ void belief_update_block(const BeliefModel& m, const float* __restrict__ obs,
                                     int n_obs, double* __restrict__ log_belief,
                                     double* __restrict__ belief_out, BeliefShared& sh) {
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int G = m.G, B = m.B, J = G * B;
+  const int G = m.G, B = m.B, U = m.U, J = G * B;
+  const int gchunk = max(1, kDeltaSlots / U);
   constexpr int kPerThread = CAP_MAX_J / kBeliefThreads;
   double acc[kPerThread];
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) acc[r] = 0.0;
-  for (int t0 = 0; t0 < n_obs; t0 += kBeliefChunk) {
-    const int nt = min(kBeliefChunk, n_obs - t0);
-    // one thread per (transition, goal, beta): the K distances of (t, g) are
-    // recomputed per beta so that the B log-sum-exps run in parallel
-    for (int item = tid; item < nt * J; item += nthr) {
-      const int tl = item / J, j = item - tl * J, g = j / B, b = j - g * B, t = t0 + tl;
-      const float zx = obs[2 * t], zy = obs[2 * t + 1];
-      const int ks = recover_control(m, obs[2 * t + 2] - zx, obs[2 * t + 3] - zy);
-      sh.ell[tl * J + j] = policy_term_one(m, zx, zy, ks, m.gx[g], m.gy[g], m.beta[b]);
-    }
-    __syncthreads();
+  for (int t = 0; t < n_obs; ++t) {
+    const float zx = obs[2 * t], zy = obs[2 * t + 1];
+    const int ks = recover_control(m, obs[2 * t + 2] - zx, obs[2 * t + 3] - zy);
+    if (ks < 0) continue;  // no displacement: no information (uniform across the block)
+    for (int g0 = 0; g0 < G; g0 += gchunk) {
+      const int gn = min(gchunk, G - g0);
+      for (int item = tid; item < gn * U; item += nthr) {
+        const int gl = item / U, u = item - gl * U;
+        const GoalOffset o = goal_offset(zx, zy, m.gx[g0 + gl], m.gy[g0 + gl]);
+        sh.dl[item] = policy_delta(o, m.sx[u], m.sy[u]);
+      }
+      __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kPerThread; ++r) {
-      const int j = tid + r * nthr;
-      if (j < J)
-        for (int tl = 0; tl < nt; ++tl) acc[r] += sh.ell[tl * J + j];
+      for (int r = 0; r < kPerThread; ++r) {
+        const int j = tid + r * nthr, g = j / B;
+        if (j < J && g >= g0 && g < g0 + gn)
+          acc[r] += policy_term_from(sh.dl + (g - g0) * U, U, ks, (double)m.beta[j - g * B]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   double v[kPerThread];
   double mx = -INFINITY;
