@@ -150,7 +150,8 @@ class Server:
                  stationary: Optional[Tuple[float, int]] = None,
                  goal_departure: Optional[float] = None, device="cuda",
                  freeze_gc: bool = True, history: int = 1 << 16,
-                 union: Optional[Tuple[Sequence, int]] = None, clock=time.perf_counter):
+                 union: Optional[Tuple[Sequence, int]] = None, clock=time.perf_counter,
+                 first_cycle: int = 0):
         """stationary = (eps, mask): a human whose newest observed step is shorter
         than eps metres is predicted with the allowed speeds `mask` only (Q = -inf
         for the others, Sec. IV-B) until it moves again.  goal_departure = r: a
@@ -163,7 +164,9 @@ class Server:
         point-wise maximum of the probabilities of the humans whose grid is
         `frame` (the planner's single occupancy map of Sec. IV-B), read with
         union_grid(cycle).  clock: the host clock of release and completion
-        times (seconds)."""
+        times (seconds).  first_cycle: number of the first cycle (a server that
+        resumes humans from carried state continues the cycle numbering, which
+        keys the random streams)."""
         tuning = tuning or {}
         self.plan = capred.Plan(K, speed, dt, n_slots, max_obs=1, ring=ring,
                                 max_smooth_radius=max_smooth_radius, speeds=speeds, **tuning)
@@ -198,7 +201,7 @@ class Server:
         # write to a slot's buffers, see _after_current_stream).
         self._dep: Optional[torch.cuda.Event] = None
         self._after_current_stream()
-        self.cycle = 0
+        self.cycle = int(first_cycle)
         self.records: collections.deque = collections.deque(maxlen=max(1, history))
         self._pending: collections.deque = collections.deque()
         if freeze_gc:

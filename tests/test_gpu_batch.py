@@ -451,6 +451,74 @@ def test_churn_with_cycles_in_flight_matches_alone(orc, cap):
         alone.close()
 
 
+def test_shifted_human_in_a_mix_matches_alone(orc, cap):
+    """One human's beta grid reaches beta v dt = 96 > 80, so its draws need the
+    max-shifted exponent (a separately compiled rollout variant).  The mixed
+    launch then runs that variant; the other humans' tiles take the unshifted
+    body inside it, so every human's grids and posterior equal those of the
+    same human served alone, bit for bit."""
+    humans = small_scene(n=4, N_div=16, H=20)
+    humans[1].beta = np.array([0.5, 50.0, 4000.0], np.float32)
+    tr = tracks_for(orc, humans, 5)
+    note("shifted-exponent human in a mix of 4 vs each alone, 3 cycles")
+    mix = make_server(cap, humans)
+    for h in humans:
+        mix.submit(request(cap, h, tr[h.hid][0]))
+    got = {h.hid: [] for h in humans}
+    for c in range(3):
+        mix.step({h.hid: tr[h.hid][c + 1] for h in humans})
+        mix.drain()
+        for h in humans:
+            got[h.hid].append(snapshot(mix, h.hid, c))
+    mix.close()
+    for h in humans:
+        alone = make_server(cap, [h], slots=1)
+        alone.submit(request(cap, h, tr[h.hid][0]))
+        for c in range(3):
+            alone.step({h.hid: tr[h.hid][c + 1]})
+            alone.drain()
+            for u, v in zip(snapshot(alone, h.hid, c), got[h.hid][c]):
+                assert np.array_equal(u, v), (h.hid, c)
+        alone.close()
+
+
+def test_resume_from_carried_state(orc, cap):
+    """Checkpoint / resume of a served human: its carried state is the log
+    posterior, the last observed position and the cycle number (the random
+    streams are keyed by human id, cycle and seed).  A new server that starts
+    at that cycle with that state reproduces the uninterrupted run bit for
+    bit, in a different slot and mix."""
+    humans = small_scene(n=3, N_div=16, H=20)
+    x = humans[1]
+    tr = tracks_for(orc, humans, 12)
+    note("resume a human from its log posterior, last position and cycle")
+    A = make_server(cap, humans)
+    for h in humans:
+        A.submit(request(cap, h, tr[h.hid][0]))
+    ref, lb6 = {}, None
+    for c in range(10):
+        A.step({h.hid: tr[h.hid][c + 1] for h in humans})
+        A.drain()
+        if c == 5:
+            lb6 = A.log_belief(x.hid).cpu().numpy().copy()
+        if c >= 6:
+            ref[c] = snapshot(A, x.hid, c)
+    A.close()
+    from paper_2603_01122_amd.serve import HumanRequest, Server
+    B = Server(x.K, x.speed, x.dt, 2, x.H, 256, 256, 6, 9, first_cycle=6)
+    other = humans[2]
+    B.submit(request(cap, other, tr[other.hid][5]))     # takes slot 0: x lands in slot 1
+    B.submit(HumanRequest(x.hid, cap.model_of(x), x.grid, x.N, x.H, tr[x.hid][6],
+                          log_belief=lb6))
+    for c in range(6, 10):
+        B.step({x.hid: tr[x.hid][c + 1], other.hid: tr[other.hid][c]})
+        B.drain()
+        assert B.slot_of[x.hid] == 1
+        for u, v in zip(snapshot(B, x.hid, c), ref[c]):
+            assert np.array_equal(u, v), c
+    B.close()
+
+
 def test_two_streams_overlap_equals_one(orc, cap):
     humans = small_scene(n=4, N_div=4, H=40)
     tr = tracks_for(orc, humans, 10)
