@@ -68,17 +68,25 @@ def algorithmic_slots(K: int, r: dict):
     return issue, pipe
 
 
-def resource_use(rates, K, psteps, seconds, traffic):
+def resource_use(rates, K, psteps, seconds, counters):
     """Each resource of the rollout against its peak over one launch: VALU
     issue and the transcendental pipe (algorithmic slots, see algorithmic_ops),
     LDS atomics (one add per particle-step into the step's window; the probe's
-    scattered-address LDS atomic rate is the peak) and HBM bytes (the profiled
-    traffic, if current; 8 TB/s)."""
+    scattered-address LDS atomic rate is the peak), device-scope global
+    atomics (the profiled count per launch against the probe's rate) and HBM
+    bytes (the profiled traffic against 8 TB/s).  counters: the profiled
+    {"traffic", "global_atomics"} per launch, if current, else None."""
     issue, pipe = algorithmic_slots(K, rates)
+    traffic = None if counters is None else counters["traffic"]
+    atomics = None if counters is None else counters["global_atomics"]
     out = {"valu_issue": round(issue * psteps / seconds / PEAK_LANE_OPS, 4),
            "transcendental_pipe": round(pipe * psteps / seconds / PEAK_LANE_OPS, 4),
            "lds_atomic": round(psteps / seconds / rates["lds_atomic_lane_ops_per_s"], 4),
            "lds_atomic_peak_lane_ops_per_s": float(f"{rates['lds_atomic_lane_ops_per_s']:.4e}"),
+           "global_atomic": None if atomics is None else
+           round(atomics / seconds / rates["global_atomic_per_s"], 4),
+           "global_atomics_per_launch": atomics,
+           "global_atomic_peak_per_s": float(f"{rates['global_atomic_per_s']:.4e}"),
            "hbm": None if traffic is None else round(traffic / seconds / 8e12, 5)}
     return out
 
@@ -103,6 +111,22 @@ def measure_rates(capred, torch) -> dict:
     rates = {k: out["fma"] / v for k, v in out.items()}
     rates["fma_lane_ops_per_s"] = out["fma"]
     rates["lds_atomic_lane_ops_per_s"] = out["lds_atomic"]
+    # device-scope atomic adds at scattered addresses over one 512x512 step
+    # grid (1 MiB) and over a 1 GiB footprint; the faster is the peak
+    iters = 64
+    for log2w, name in ((18, "1MiB"), (28, "1GiB")):
+        counts = torch.zeros(1 << log2w, dtype=torch.int32, device="cuda")
+        capred.probe_global_atomic(4, blocks, counts)
+        e0.record()
+        capred.probe_global_atomic(iters, blocks, counts)
+        e1.record()
+        torch.cuda.synchronize()
+        rates[f"global_atomic_{name}_per_s"] = blocks * 256 * 8 * iters / (e0.elapsed_time(e1) * 1e-3)
+        total = int(counts.sum(dtype=torch.int64))
+        assert total == blocks * 256 * 8 * (iters + 4), "global atomic probe lost adds"
+        del counts
+    rates["global_atomic_per_s"] = max(rates["global_atomic_1MiB_per_s"],
+                                       rates["global_atomic_1GiB_per_s"])
     return rates
 
 
@@ -186,9 +210,11 @@ def cpu_baseline(scene, max_seconds, n_cycles=10):
             "cpu_model": cpu_model()}
 
 
-def profiled_traffic(best):
-    """HBM bytes per rollout launch from the committed counter summary, if the
-    rollout's sources and the launch shape are those the counters were taken on."""
+def profiled_counters(best, scene="16humans"):
+    """HBM bytes and device-scope atomics per rollout launch of a scene
+    ("16humans" or "64humans") from the committed counter summary, if the
+    rollout's sources and the scene's launch shape are those the counters were
+    taken on; else None."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "plan_rollout_kernel_16humans_counters.md")
@@ -196,10 +222,12 @@ def profiled_traffic(best):
         text = open(path).read()
     except OSError:
         return None
+    pre = "" if scene == "16humans" else "scene64_"
+    keys = ("source_sha256", "sources", pre + "tuning", pre + "traffic_bytes_per_launch",
+            pre + "global_atomics_per_launch")
     fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "source_sha256",
-                                                 "sources", "tuning"))
-    if len(fields) != 4:
+                  if line.split(": ", 1)[0] in keys)
+    if len(fields) != len(keys):
         return None
     h = hashlib.sha256()
     for src in fields["sources"].split():
@@ -207,9 +235,12 @@ def profiled_traffic(best):
             h.update(f.read())
     shape = "block_threads=%s particles_per_thread=%s" % (
         best.get("block_threads"), best.get("particles_per_thread"))
-    if h.hexdigest() != fields["source_sha256"].strip() or shape != fields["tuning"].strip():
+    if best.get("lds_bytes") is not None:
+        shape += " lds_bytes=%s" % best["lds_bytes"]
+    if h.hexdigest() != fields["source_sha256"].strip() or shape != fields[pre + "tuning"].strip():
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return {"traffic": int(fields[pre + "traffic_bytes_per_launch"]),
+            "global_atomics": int(fields[pre + "global_atomics_per_launch"])}
 
 
 def mppi_timing(capred, torch, np, srv, humans, cycle, reps=20):
@@ -347,7 +378,8 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
     psteps = sc.particle_steps
     W = algorithmic_ops(humans[0].K, rates)
     achieved = W * psteps / roll
-    resources = resource_use(rates, humans[0].K, psteps, roll, None)
+    counters = profiled_counters(shape, "64humans")
+    resources = resource_use(rates, humans[0].K, psteps, roll, counters)
     return {"workload": "64 humans x 2^20 particles, 6 goals, 9 beta, K=32, v=1.2 m/s, "
                         "dt=0.01 s, H=200, 512x512 grids at 0.02 m",
             "particle_steps_per_cycle": psteps, "cycles": cycles,
@@ -361,6 +393,7 @@ def largest_scene(capred, torch, np, tune, scenes, rates, cycles):
                          "achieved": round(achieved / 1e12, 3),
                          "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
                          "frac": round(achieved / PEAK_LANE_OPS, 4),
+                         "traffic": None if counters is None else counters["traffic"],
                          "resources": resources}}
 
 
@@ -604,7 +637,8 @@ def main():
     roll = float(np.mean(durs))
     W = algorithmic_ops(humans[0].K, rates)
     achieved = W * psteps / roll
-    traffic = profiled_traffic(best)
+    counters = profiled_counters(best)
+    traffic = None if counters is None else counters["traffic"]
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
                 "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": traffic,
@@ -617,7 +651,9 @@ def main():
                 "rates_vs_fma": {k: round(v, 3) for k, v in rates.items()
                                  if not k.endswith("_per_s")},
                 "fma_lane_ops_per_s": float(f"{rates['fma_lane_ops_per_s']:.4e}"),
-                "resources": resource_use(rates, humans[0].K, psteps, roll, traffic)}
+                "global_atomic_per_s": {k: float(f"{rates[f'global_atomic_{k}_per_s']:.4e}")
+                                        for k in ("1MiB", "1GiB")},
+                "resources": resource_use(rates, humans[0].K, psteps, roll, counters)}
     log(f"rollout kernel {roll * 1e3:.3f} ms, {W:.1f} ops/particle-step, frac {achieved / PEAK_LANE_OPS:.3f}")
 
     # ---------------------------------------------------------- paced 125 Hz serving

@@ -414,8 +414,16 @@ cap_status cap_mppi_step(const double z0[4], const double goal[4], int32_t T, do
  * 6 one exp2 with one multiply and three FMA (mixed issue).
  * Time it with events on `stream`; sink_dev is a [blocks] FP32 buffer that is
  * written only to keep the chains alive.  cap_copy is a plain device copy of
- * `bytes` (16-byte aligned), used to calibrate hardware byte counters. */
+ * `bytes` (16-byte aligned), used to calibrate hardware byte counters.
+ * cap_probe_global_atomic runs `blocks` x 256 threads, each issuing 8 chains
+ * of `iters` relaxed device-scope adds of 1 (no return value, as the
+ * histogram flush issues them) to pseudo-random words of counts_dev, a
+ * caller-owned device buffer of 2^log2_words uint32 (log2_words in [6, 30]);
+ * after the launch the words sum to blocks * 2048 * iters more than before.
+ * Errors: CAP_E_INVALID for a null buffer or out-of-range arguments. */
 cap_status cap_probe(int32_t kind, int64_t iters, int32_t blocks, float* sink_dev, void* stream);
+cap_status cap_probe_global_atomic(int64_t iters, int32_t blocks, uint32_t* counts_dev,
+                                   int32_t log2_words, void* stream);
 cap_status cap_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
 
 #ifdef __cplusplus

@@ -110,8 +110,9 @@ _sig("cap_loglik_backward_noalloc", _i32, _i32, _d, _d, _vp, _vp, _i32, _i32, _v
      _i32, _vp, _vp, _vp, _vp)
 _sig("cap_philox_blocks", _i32, _i64, _u32, _u32, _u32, _u32, _u64, _vp, _vp)
 _sig("cap_probe", _i32, _i32, _i64, _i32, _vp, _vp)
+_sig("cap_probe_global_atomic", _i32, _i64, _i32, _vp, _i32, _vp)
 _sig("cap_copy", _i32, _vp, _vp, _sz, _vp)
-EXPORTED = ["cap_probe", "cap_copy", "cap_philox_blocks", "cap_abi_version", "cap_last_error", "cap_device_cu_count", "cap_belief_update",
+EXPORTED = ["cap_probe", "cap_probe_global_atomic", "cap_copy", "cap_philox_blocks", "cap_abi_version", "cap_last_error", "cap_device_cu_count", "cap_belief_update",
             "cap_belief_reset", "cap_predict_occupancy", "cap_normalize", "cap_simulate_tracks",
             "cap_loglik", "cap_loglik_backward", "cap_loglik_backward_workspace",
             "cap_loglik_backward_noalloc",
@@ -365,6 +366,17 @@ def probe(kind: str, iters: int, blocks: int, sink: torch.Tensor, stream=None):
     """Launches one throughput probe (8 chains x iters ops per thread, 256 threads/block)."""
     _check(_lib.cap_probe(PROBE_KINDS[kind], iters, blocks, _ptr(sink, torch.float32, "sink"),
                           _stream(stream)), "cap_probe")
+
+
+def probe_global_atomic(iters: int, blocks: int, counts: torch.Tensor, stream=None):
+    """Launches the device-scope atomic-add probe (8 chains x iters adds per
+    thread, 256 threads/block) over counts, an int32 buffer of 2^k words."""
+    n = counts.numel()
+    if n & (n - 1) or not 64 <= n <= 1 << 30:
+        raise ValueError("counts must hold 2^k words, k in [6, 30]")
+    _check(_lib.cap_probe_global_atomic(iters, blocks, _ptr(counts, torch.int32, "counts"),
+                                        n.bit_length() - 1, _stream(stream)),
+           "cap_probe_global_atomic")
 
 
 def copy(src: torch.Tensor, dst: torch.Tensor, stream=None):

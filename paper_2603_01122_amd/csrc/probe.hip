@@ -1,7 +1,8 @@
 // probe.hip -- throughput probes for the roofline of the rollout: FP32 FMA,
 // the three transcendentals of a heading evaluation (exp2, sqrt, rcp), the
-// 32x32->64 multiply of Philox, LDS atomics, and a plain copy kernel whose
-// known traffic calibrates the HBM byte counters.
+// 32x32->64 multiply of Philox, LDS atomics, device-scope global atomics (the
+// histogram flush), and a plain copy kernel whose known traffic calibrates
+// the HBM byte counters.
 #include <algorithm>
 
 #include "common.hpp"
@@ -56,6 +57,26 @@ __global__ void __launch_bounds__(256) probe_kernel(int64_t iters, float seed,
   if (acc == 123.456f) sink[blockIdx.x] = acc;  // keeps the chains alive
 }
 
+// Relaxed device-scope adds without return, as the histogram flush issues
+// them: every lane of every chain draws a fresh address from its own linear
+// congruential sequence and adds 1 to that word of a 2^log2_words buffer (the
+// top bits of the state; lanes of a wave land on different lines).
+__global__ void __launch_bounds__(256) probe_global_atomic_kernel(int64_t iters,
+                                                                  uint32_t* __restrict__ counts,
+                                                                  uint32_t shift) {
+  uint32_t u[kProbeChains];
+  const uint32_t lane = blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) u[c] = lane * 2654435761u + (uint32_t)c * 0x9E3779B9u;
+  for (int64_t i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) {
+      u[c] = u[c] * 1664525u + 1013904223u;
+      global_add(counts + (u[c] >> shift), 1u);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) copy_kernel(const uint4* __restrict__ a,
                                                    uint4* __restrict__ b, size_t n16) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -69,7 +90,7 @@ using namespace capred;
 extern "C" cap_status cap_probe(int32_t kind, int64_t iters, int32_t blocks, float* sink_dev,
                                 void* stream) {
   if (kind < 0 || kind > 6 || iters < 1 || blocks < 1 || !sink_dev)
-    return fail(CAP_E_INVALID, "probe: kind in [0,5], iters >= 1, blocks >= 1, sink required");
+    return fail(CAP_E_INVALID, "probe: kind in [0,6], iters >= 1, blocks >= 1, sink required");
   hipStream_t s = as_stream(stream);
   const dim3 g((unsigned)blocks), b(256);
   switch (kind) {
@@ -81,6 +102,17 @@ extern "C" cap_status cap_probe(int32_t kind, int64_t iters, int32_t blocks, flo
     case 5: hipLaunchKernelGGL(probe_kernel<5>, g, b, 0, s, iters, 0.5f, sink_dev); break;
     default: hipLaunchKernelGGL(probe_kernel<6>, g, b, 0, s, iters, 0.5f, sink_dev); break;
   }
+  CAP_HIP(hipGetLastError());
+  return CAP_OK;
+}
+
+extern "C" cap_status cap_probe_global_atomic(int64_t iters, int32_t blocks, uint32_t* counts_dev,
+                                               int32_t log2_words, void* stream) {
+  if (iters < 1 || blocks < 1 || !counts_dev || log2_words < 6 || log2_words > 30)
+    return fail(CAP_E_INVALID,
+                "probe_global_atomic: iters >= 1, blocks >= 1, log2_words in [6,30], buffer required");
+  hipLaunchKernelGGL(probe_global_atomic_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     as_stream(stream), iters, counts_dev, (uint32_t)(32 - log2_words));
   CAP_HIP(hipGetLastError());
   return CAP_OK;
 }

@@ -157,3 +157,16 @@ def test_invalid_mppi(cap):
              None) == cap.CAP_E_INVALID                                   # misaligned delta
     assert f(z, z, 4, 0.1, 8, p, p, p, 3, None, C.byref(cost(1.0)), p, None) == \
         cap.CAP_E_INVALID                                                 # occupancy, no grid
+
+
+def test_invalid_probe_arguments(cap):
+    """The measurement probes validate their arguments before any launch."""
+    p = C.c_void_p(256)
+    f = cap._lib.cap_probe_global_atomic
+    assert f(1, 1, None, 10, None) == cap.CAP_E_INVALID          # no buffer
+    assert f(1, 1, p, 5, None) == cap.CAP_E_INVALID              # below 2^6 words
+    assert f(1, 1, p, 31, None) == cap.CAP_E_INVALID             # above 2^30 words
+    assert f(0, 1, p, 10, None) == cap.CAP_E_INVALID
+    assert f(1, 0, p, 10, None) == cap.CAP_E_INVALID
+    assert cap._lib.cap_probe(7, 1, 1, p, None) == cap.CAP_E_INVALID
+    assert cap._lib.cap_probe(0, 1, 1, None, None) == cap.CAP_E_INVALID
