@@ -2,7 +2,11 @@
 
 Every translation unit is compiled for gfx950 only, with packed-FP32 VALU
 instructions disabled (-packed-fp32-ops), then linked into one shared library
-next to this file.
+next to this file.  The two units holding particle rollouts are scheduled with
+LLVM's iterative ILP strategy, which interleaves the independent draw chains
+of a thread's particles more than the default occupancy-first strategy (the
+rollout kernels run at four waves per SIMD whatever their register count up to
+128, so the extra registers cost no occupancy).
 """
 from __future__ import annotations
 
@@ -34,9 +38,15 @@ def compile_flags():
             "-I", os.path.join(HERE, "..", "include")]
 
 
+# per-unit scheduling strategy (see the module docstring)
+EXTRA_FLAGS = {src: ["-mllvm", "--amdgpu-sched-strategy=iterative-ilp"]
+               for src in ("plan.hip", "predict.hip")}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *compile_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *compile_flags(), *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src),
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -259,6 +259,62 @@ __device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float 
   }
 }
 
+// Two particles' draws in one pass: the same operations as draw_heading<KT,
+// SHIFT> for each particle, in the same order (so the same headings bit for
+// bit), with the two particles' heading terms side by side, which gives the
+// scheduler two independent sqrt -> rcp -> exp2 chains to interleave.
+template <int KT, bool SHIFT>
+__device__ __forceinline__ void draw_heading_pair(const float ax[2], const float ay[2],
+                                                  const float ib[2], const float u[2],
+                                                  const HeadingTable& T, int k_out[2]) {
+  static_assert(KT > 0 && KT % 2 == 0, "paired draw needs a compile-time, point-symmetric table");
+  constexpr int KH = KT / 2;
+  float D2[2], Dib[2], ax2[2], ay2[2], acc[2];
+  float C[2][KT];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    D2[m] = fmaf(ax[m], ax[m], ay[m] * ay[m]);
+    Dib[m] = fast_sqrt(D2[m]) * ib[m];
+    ax2[m] = ax[m] + ax[m];
+    ay2[m] = ay[m] + ay[m];
+  }
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const float dot = fmaf(ax2[m], T.fx[k], ay2[m] * T.fy[k]);
+      const float np = T.s2[k] + dot, nm = T.s2[k] - dot;
+      const float dp = fast_sqrt(fabsf(D2[m] + np)), dm = fast_sqrt(fabsf(D2[m] + nm));
+      C[m][k] = np * fast_rcp(fmaf(dp, ib[m], Dib[m]));
+      C[m][k + KH] = nm * fast_rcp(fmaf(dm, ib[m], Dib[m]));
+    }
+  }
+  if constexpr (SHIFT) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float mx = C[m][0];
+#pragma unroll
+      for (int k = 1; k < KT; ++k) mx = fmaxf(mx, C[m][k]);
+#pragma unroll
+      for (int k = 0; k < KT; ++k) C[m][k] -= mx;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    acc[m] = fast_exp2(C[m][0]);
+    C[m][0] = acc[m];
+  }
+#pragma unroll
+  for (int k = 1; k < KT; ++k)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      acc[m] += fast_exp2(C[m][k]);
+      C[m][k] = acc[m];
+    }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) k_out[m] = cdf_index<KT>(C[m], u[m] * acc[m], KT);
+}
+
 // Multi-speed draw: the inverse CDF over all U = S KT controls (u = s KT + k,
 // prefix sums in u order) in two passes.  Pass 1 accumulates the weights of
 // every allowed speed block in u order and keeps the running sum at the end of

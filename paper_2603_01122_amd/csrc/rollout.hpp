@@ -99,7 +99,11 @@ __host__ __device__ constexpr size_t window_lds_bytes(int cap, int particles_per
 // MS (several speeds): draw_control over the S K controls; `ctl` is an LDS
 // array of CAP_MAX_U float4 that receives (fx, fy, s2) of every control, read
 // per lane for the block recomputation and the step (unused otherwise).
-template <int KT, int P, bool SHIFT, bool MS>
+//
+// PAIR: draw the particles two at a time (draw_heading_pair), for fixed K of
+// at most 16 without the shifted exponent, where the two chains fit in the
+// registers of four waves per SIMD without spilling.
+template <int KT, int P, bool SHIFT, bool MS, bool PAIR>
 __device__ __forceinline__ void rollout_tile_body(const RolloutDesc& d, int64_t first,
                                                   uint32_t seed_lo, uint32_t seed_hi,
                                                   TileShared& sh, uint32_t* win, int cap,
@@ -196,28 +200,70 @@ __device__ __forceinline__ void rollout_tile_body(const RolloutDesc& d, int64_t 
     if (single) __syncthreads();
     uint32_t* grid_t = d.counts + (size_t)(t - 1) * plane;
     bool off_any = false;
+    // Draws of all P particles first, then their emplacement: the draws are
+    // independent dependency chains (transcendental latency), which the
+    // scheduler can interleave only while no branch separates them.  Each
+    // particle's step word is rw[p].x; the remaining words move down, so the
+    // word is picked without branching on the step's phase.
+    int kk[P];
+    if constexpr (PAIR) {
+      static_assert(P % 2 == 0 && !MS, "paired draws need an even P and one speed");
+#pragma unroll
+      for (int p = 0; p < P; p += 2) {
+        float ax[2], ay[2], ibm[2], um[2];
+        int ko[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          ax[m] = (float)(X[p + m] - GXp[p + m]);
+          ay[m] = (float)(Y[p + m] - GYp[p + m]);
+          ibm[m] = ib[p + m];
+          um[m] = uniform24f(rw[p + m].x);
+          rw[p + m] = make_uint4(rw[p + m].y, rw[p + m].z, rw[p + m].w, 0u);
+        }
+        draw_heading_pair<KT, SHIFT>(ax, ay, ibm, um, d.T, ko);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const int2 st = sh.S[ko[m]];
+          X[p + m] += st.x;
+          Y[p + m] += st.y;
+          kk[p + m] = ko[m];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        // computed for inactive lanes too (harmless state), so that the P
+        // particles stay in one basic block; only emplacement is predicated
+        const float u = uniform24f(rw[p].x);
+        rw[p] = make_uint4(rw[p].y, rw[p].z, rw[p].w, 0u);
+        int k;
+        if constexpr (MS)
+          k = draw_control<KT, SHIFT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p], u,
+                                      d.T, d.S, d.smask, d.s_last, ctl);
+        else
+          k = draw_heading<KT, SHIFT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p], u,
+                                      d.T, d.K);
+        if constexpr (MS) {
+          const float4 c = ctl[k];
+          X[p] += (int32_t)c.x;
+          Y[p] += (int32_t)c.y;
+        } else {
+          const int2 st = sh.S[k];
+          X[p] += st.x;
+          Y[p] += st.y;
+        }
+        kk[p] = k;
+      }
+    }
+    // The draws' results are fixed here (an empty asm that reads and writes
+    // them), so that the compiler does not sink each draw into the branchy
+    // emplacement of its particle below.
+#pragma unroll
+    for (int p = 0; p < P; ++p) asm volatile("" : "+v"(X[p]), "+v"(Y[p]), "+v"(kk[p]));
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       bool off = false;
-      // computed for inactive lanes too (harmless state), so that the P
-      // particles stay in one basic block; only emplacement is predicated
-      const float u = uniform24f(pick_word(rw[p], s));
-      int k;
-      if constexpr (MS)
-        k = draw_control<KT, SHIFT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p], u, d.T,
-                                    d.S, d.smask, d.s_last, ctl);
-      else
-        k = draw_heading<KT, SHIFT>((float)(X[p] - GXp[p]), (float)(Y[p] - GYp[p]), ib[p], u,
-                                    d.T, d.K);
-      if constexpr (MS) {
-        const float4 c = ctl[k];
-        X[p] += (int32_t)c.x;
-        Y[p] += (int32_t)c.y;
-      } else {
-        const int2 st = sh.S[k];
-        X[p] += st.x;
-        Y[p] += st.y;
-      }
+      const int k = kk[p];
       bool fresh = false;     // this lane turned an empty window word non-empty
       uint32_t widx = 0;
       if (act[p]) {
@@ -297,11 +343,12 @@ __device__ __forceinline__ void rollout_tile(const RolloutDesc& d, int64_t first
                                              int cap, float4* ctl) {
   if constexpr (SHIFT) {
     if (!d.shift) {
-      rollout_tile_body<KT, P, false, MS>(d, first, seed_lo, seed_hi, sh, win, cap, ctl);
+      rollout_tile_body<KT, P, false, MS, false>(d, first, seed_lo, seed_hi, sh, win, cap, ctl);
       return;
     }
   }
-  rollout_tile_body<KT, P, SHIFT, MS>(d, first, seed_lo, seed_hi, sh, win, cap, ctl);
+  constexpr bool kPair = !SHIFT && !MS && KT > 0 && KT <= 16 && P % 2 == 0;
+  rollout_tile_body<KT, P, SHIFT, MS, kPair>(d, first, seed_lo, seed_hi, sh, win, cap, ctl);
 }
 
 }  // namespace capred
