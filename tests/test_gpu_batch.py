@@ -74,12 +74,18 @@ def snapshot(srv, hid, c):
             post.cpu().numpy().copy())
 
 
-def test_batched_equals_plain_and_single(orc, cap):
+@pytest.mark.parametrize("shape", [{}, dict(block_threads=256, particles_per_thread=4),
+                                   dict(block_threads=512, particles_per_thread=2)])
+def test_batched_equals_plain_and_single(orc, cap, shape):
+    """Batched, per-human and single-human launches give the same bits.  With
+    an even number of particles per thread the K = 16 rollout draws two
+    particles per pass (their heading chains side by side); the single-human
+    entry point draws one particle at a time."""
     humans = small_scene()
     tr = tracks_for(orc, humans, 8)
-    note("batched vs plain vs single, 6 humans x 4 cycles")
-    A = make_server(cap, humans)
-    Bp = make_server(cap, humans)
+    note(f"batched vs plain vs single, 6 humans x 4 cycles, shape {shape or 'default'}")
+    A = make_server(cap, humans, **shape)
+    Bp = make_server(cap, humans, **shape)
     for h in humans:
         A.submit(request(cap, h, tr[h.hid][0]))
         Bp.submit(request(cap, h, tr[h.hid][0]))
