@@ -202,86 +202,30 @@ __device__ __forceinline__ int cdf_index(const float* C, float thr, int Krt) {
 //
 // SHIFT (a compile-time variant, used when beta * step is large enough for
 // exp2 to overflow) subtracts the largest exponent before exponentiating.
-template <int KT, bool SHIFT>
-__device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float u,
-                                            const HeadingTable& T, int Krt) {
-  constexpr int KM = KT > 0 ? KT : CAP_MAX_K;
-  const int K = KT > 0 ? KT : Krt;
-  const float D2 = fmaf(ax, ax, ay * ay);
-  const float D = fast_sqrt(D2);
-  const float Dib = D * ib;
-  const float ax2 = ax + ax, ay2 = ay + ay;
-  float C[KM];
-  float acc = 0.f;
-  if constexpr (KT > 0) {
-    constexpr int KH = KT / 2;
-    // exponents of both halves, then the prefix sum in heading order
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const float dot = fmaf(ax2, T.fx[k], ay2 * T.fy[k]);
-      const float np = T.s2[k] + dot, nm = T.s2[k] - dot;
-      const float dp = fast_sqrt(fabsf(D2 + np)), dm = fast_sqrt(fabsf(D2 + nm));
-      C[k] = np * fast_rcp(fmaf(dp, ib, Dib));
-      C[k + KH] = nm * fast_rcp(fmaf(dm, ib, Dib));
-    }
-    if constexpr (SHIFT) {
-      float m = C[0];
-#pragma unroll
-      for (int k = 1; k < KT; ++k) m = fmaxf(m, C[k]);
-#pragma unroll
-      for (int k = 0; k < KT; ++k) C[k] -= m;
-    }
-    acc = fast_exp2(C[0]);
-    C[0] = acc;
-#pragma unroll
-    for (int k = 1; k < KT; ++k) {
-      acc += fast_exp2(C[k]);
-      C[k] = acc;
-    }
-    return cdf_index<KT>(C, u * acc, Krt);
-  } else {
-    float m = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-      if (k >= K) break;
-      const float n = fmaf(ax2, T.fx[k], fmaf(ay2, T.fy[k], T.s2[k]));
-      const float d = fast_sqrt(fabsf(D2 + n));
-      C[k] = n * fast_rcp(fmaf(d, ib, Dib));
-      if constexpr (SHIFT) m = fmaxf(m, C[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-      if (k >= K) break;
-      acc += fast_exp2(SHIFT ? C[k] - m : C[k]);
-      C[k] = acc;
-    }
-    return cdf_index<KT>(C, u * acc, Krt);
-  }
-}
-
-// Two particles' draws in one pass: the same operations as draw_heading<KT,
-// SHIFT> for each particle, in the same order (so the same headings bit for
-// bit), with the two particles' heading terms side by side, which gives the
-// scheduler two independent sqrt -> rcp -> exp2 chains to interleave.
-template <int KT, bool SHIFT>
-__device__ __forceinline__ void draw_heading_pair(const float ax[2], const float ay[2],
-                                                  const float ib[2], const float u[2],
-                                                  const HeadingTable& T, int k_out[2]) {
-  static_assert(KT > 0 && KT % 2 == 0, "paired draw needs a compile-time, point-symmetric table");
+//
+// draw_headings: M particles' draws in one pass (KT > 0): the operations of each particle
+// are the same and in the same order for every M, so its heading is the same
+// bit for bit; with M = 2 the two particles' heading terms stand side by side,
+// which gives the scheduler two independent sqrt -> rcp -> exp2 chains.
+template <int KT, bool SHIFT, int M>
+__device__ __forceinline__ void draw_headings(const float* ax, const float* ay, const float* ib,
+                                              const float* u, const HeadingTable& T, int* k_out) {
+  static_assert(KT > 0 && KT % 2 == 0, "needs a compile-time, point-symmetric table");
   constexpr int KH = KT / 2;
-  float D2[2], Dib[2], ax2[2], ay2[2], acc[2];
-  float C[2][KT];
+  float D2[M], Dib[M], ax2[M], ay2[M], acc[M];
+  float C[M][KT];
 #pragma unroll
-  for (int m = 0; m < 2; ++m) {
+  for (int m = 0; m < M; ++m) {
     D2[m] = fmaf(ax[m], ax[m], ay[m] * ay[m]);
     Dib[m] = fast_sqrt(D2[m]) * ib[m];
     ax2[m] = ax[m] + ax[m];
     ay2[m] = ay[m] + ay[m];
   }
+  // exponents of both halves, then the prefix sum in heading order
 #pragma unroll
   for (int k = 0; k < KH; ++k) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < M; ++m) {
       const float dot = fmaf(ax2[m], T.fx[k], ay2[m] * T.fy[k]);
       const float np = T.s2[k] + dot, nm = T.s2[k] - dot;
       const float dp = fast_sqrt(fabsf(D2[m] + np)), dm = fast_sqrt(fabsf(D2[m] + nm));
@@ -291,7 +235,7 @@ __device__ __forceinline__ void draw_heading_pair(const float ax[2], const float
   }
   if constexpr (SHIFT) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < M; ++m) {
       float mx = C[m][0];
 #pragma unroll
       for (int k = 1; k < KT; ++k) mx = fmaxf(mx, C[m][k]);
@@ -300,19 +244,52 @@ __device__ __forceinline__ void draw_heading_pair(const float ax[2], const float
     }
   }
 #pragma unroll
-  for (int m = 0; m < 2; ++m) {
+  for (int m = 0; m < M; ++m) {
     acc[m] = fast_exp2(C[m][0]);
     C[m][0] = acc[m];
   }
 #pragma unroll
   for (int k = 1; k < KT; ++k)
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < M; ++m) {
       acc[m] += fast_exp2(C[m][k]);
       C[m][k] = acc[m];
     }
 #pragma unroll
-  for (int m = 0; m < 2; ++m) k_out[m] = cdf_index<KT>(C[m], u[m] * acc[m], KT);
+  for (int m = 0; m < M; ++m) k_out[m] = cdf_index<KT>(C[m], u[m] * acc[m], KT);
+}
+
+template <int KT, bool SHIFT>
+__device__ __forceinline__ int draw_heading(float ax, float ay, float ib, float u,
+                                            const HeadingTable& T, int Krt) {
+  if constexpr (KT > 0) {
+    int k;
+    draw_headings<KT, SHIFT, 1>(&ax, &ay, &ib, &u, T, &k);
+    return k;
+  } else {
+    const float D2 = fmaf(ax, ax, ay * ay);
+    const float D = fast_sqrt(D2);
+    const float Dib = D * ib;
+    const float ax2 = ax + ax, ay2 = ay + ay;
+    float C[CAP_MAX_K];
+    float acc = 0.f;
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < CAP_MAX_K; ++k) {
+      if (k >= Krt) break;
+      const float n = fmaf(ax2, T.fx[k], fmaf(ay2, T.fy[k], T.s2[k]));
+      const float d = fast_sqrt(fabsf(D2 + n));
+      C[k] = n * fast_rcp(fmaf(d, ib, Dib));
+      if constexpr (SHIFT) m = fmaxf(m, C[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < CAP_MAX_K; ++k) {
+      if (k >= Krt) break;
+      acc += fast_exp2(SHIFT ? C[k] - m : C[k]);
+      C[k] = acc;
+    }
+    return cdf_index<KT>(C, u * acc, Krt);
+  }
 }
 
 // Multi-speed draw: the inverse CDF over all U = S KT controls (u = s KT + k,

@@ -100,7 +100,7 @@ __host__ __device__ constexpr size_t window_lds_bytes(int cap, int particles_per
 // array of CAP_MAX_U float4 that receives (fx, fy, s2) of every control, read
 // per lane for the block recomputation and the step (unused otherwise).
 //
-// PAIR: draw the particles two at a time (draw_heading_pair), for fixed K of
+// PAIR: draw the particles two at a time (draw_headings with M = 2), for fixed K of
 // at most 16 without the shifted exponent, where the two chains fit in the
 // registers of four waves per SIMD without spilling.
 template <int KT, int P, bool SHIFT, bool MS, bool PAIR>
@@ -220,7 +220,7 @@ __device__ __forceinline__ void rollout_tile_body(const RolloutDesc& d, int64_t 
           um[m] = uniform24f(rw[p + m].x);
           rw[p + m] = make_uint4(rw[p + m].y, rw[p + m].z, rw[p + m].w, 0u);
         }
-        draw_heading_pair<KT, SHIFT>(ax, ay, ibm, um, d.T, ko);
+        draw_headings<KT, SHIFT, 2>(ax, ay, ibm, um, d.T, ko);
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
           const int2 st = sh.S[ko[m]];
