@@ -319,6 +319,14 @@ cap_status cap_plan_reset_belief(cap_plan* plan, int32_t slot);
  * xy [n_new][2] FP32 metres (host), 0 <= n_new <= max_obs.  The first one
  * continues from the slot's last observed position. */
 cap_status cap_plan_stage_obs(cap_plan* plan, int32_t slot, const float* xy, int32_t n_new);
+/* The same for many slots in one call (a serving loop stages every human's
+ * new position each cycle): entry i stages one position xy[i] ([n][2] FP32
+ * metres, host) for slots[i] (host [n]); a slot listed twice stages two
+ * positions in list order.  Every entry is validated before any is staged, so
+ * a rejected call (inactive slot, too many staged positions, a position whose
+ * horizon leaves the lattice) stages nothing. */
+cap_status cap_plan_stage_obs_many(cap_plan* plan, int32_t n, const int32_t* slots,
+                                   const float* xy);
 /* Run one cycle on `stream`: copy the compact descriptors (with staged
  * observations) to ring entry cycle % ring and launch the captured graphs:
  * belief update -> grid clear -> persistent batched rollout -> normalisation

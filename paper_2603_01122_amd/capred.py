@@ -124,7 +124,8 @@ if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_clear_slot", _i32, _vp, _i32)
     _sig("cap_plan_set_speed_mask", _i32, _vp, _i32, _u32)
     _sig("cap_plan_reset_belief", _i32, _vp, _i32)
-    _sig("cap_plan_stage_obs", _i32, _vp, _i32, C.POINTER(C.c_float), _i32)
+    _sig("cap_plan_stage_obs", _i32, _vp, _i32, _vp, _i32)
+    _sig("cap_plan_stage_obs_many", _i32, _vp, _i32, _vp, _vp)
     _sig("cap_plan_run", _i32, _vp, _u64, _u32, _vp)
     _sig("cap_plan_run_plain", _i32, _vp, _u64, _u32, _vp)
     _sig("cap_plan_set_union", _i32, _vp, C.POINTER(cap_grid), _i32, _vp)
@@ -134,7 +135,8 @@ if hasattr(_lib, "cap_plan_create"):
     _sig("cap_plan_replay_rollout", _i32, _vp, _vp, _vp, _vp)
     _sig("cap_plan_tile_split", _i32, C.POINTER(_i32), _i32, _i32, _i32, _i32, C.POINTER(_i32))
     EXPORTED += ["cap_plan_replay_rollout", "cap_plan_create", "cap_plan_destroy", "cap_plan_set_slot",
-                 "cap_plan_clear_slot", "cap_plan_stage_obs", "cap_plan_run",
+                 "cap_plan_clear_slot", "cap_plan_stage_obs", "cap_plan_stage_obs_many",
+                 "cap_plan_run",
                  "cap_plan_run_plain", "cap_plan_sync", "cap_plan_stats", "cap_plan_tuning",
                  "cap_plan_set_speed_mask", "cap_plan_reset_belief", "cap_plan_tile_split",
                  "cap_plan_set_union"]
@@ -611,9 +613,21 @@ class Plan:
         self._union = union
 
     def stage(self, slot: int, xy):
+        # called for every human every cycle: the array's address is passed as a
+        # plain integer (a ctypes POINTER object costs several microseconds)
         a = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
-        _check(_lib.cap_plan_stage_obs(self._h, slot, a.ctypes.data_as(C.POINTER(C.c_float)),
-                                       a.shape[0]), "cap_plan_stage_obs")
+        _check(_lib.cap_plan_stage_obs(self._h, slot, a.ctypes.data, a.shape[0]),
+               "cap_plan_stage_obs")
+
+    def stage_many(self, slots, xy):
+        """One new position per listed slot in one call: slots [n] int32,
+        xy [n, 2] (metres)."""
+        sl = np.ascontiguousarray(slots, np.int32).reshape(-1)
+        a = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
+        if a.shape[0] != sl.size:
+            raise ValueError("one position per slot")
+        _check(_lib.cap_plan_stage_obs_many(self._h, sl.size, sl.ctypes.data, a.ctypes.data),
+               "cap_plan_stage_obs_many")
 
     def run(self, seed: int, cycle: int, stream=None):
         _check(_lib.cap_plan_run(self._h, seed, cycle, _stream(stream)), "cap_plan_run")

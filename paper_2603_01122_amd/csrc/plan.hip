@@ -896,6 +896,33 @@ extern "C" cap_status cap_plan_stage_obs(cap_plan* p, int32_t slot, const float*
   return CAP_OK;
 }
 
+extern "C" cap_status cap_plan_stage_obs_many(cap_plan* p, int32_t n, const int32_t* slots,
+                                              const float* xy) {
+  if (!p) return fail(CAP_E_INVALID, "plan is NULL");
+  if (n < 0) return fail(CAP_E_INVALID, "n must be >= 0");
+  if (n > 0 && (!slots || !xy)) return fail(CAP_E_INVALID, "slots or xy is NULL");
+  // validate every entry first, so that a rejected call stages nothing
+  std::vector<int32_t> adds((size_t)p->cfg.n_slots, 0);
+  for (int i = 0; i < n; ++i) {
+    const int32_t slot = slots[i];
+    if (slot < 0 || slot >= p->cfg.n_slots || !p->slots[slot].active)
+      return fail(CAP_E_INVALID, "slot is not active");
+    const HostSlot& hs = p->slots[slot];
+    if (hs.n_staged + ++adds[slot] > p->cfg.max_obs)
+      return fail(CAP_E_CAPACITY, "more staged observations than max_obs");
+    const int32_t reach = std::max(hs.tmpl.rd.Rx, hs.tmpl.rd.Ry);
+    cap_status st = check_position(hs, xy[2 * i], xy[2 * i + 1], hs.tmpl.rd.H, reach);
+    if (st != CAP_OK) return st;
+  }
+  for (int i = 0; i < n; ++i) {
+    HostSlot& hs = p->slots[slots[i]];
+    hs.staged[2 * hs.n_staged] = xy[2 * i];
+    hs.staged[2 * hs.n_staged + 1] = xy[2 * i + 1];
+    ++hs.n_staged;
+  }
+  return CAP_OK;
+}
+
 static cap_status begin_cycle(cap_plan* p, uint64_t seed, uint32_t cycle, hipStream_t s,
                               int* e_out, size_t* bytes) {
   if (cycle >= 0x7FFFFFFFu) return fail(CAP_E_INVALID, "cycle must be < 2^31 - 1");

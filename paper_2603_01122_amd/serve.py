@@ -258,10 +258,15 @@ class Server:
         """Admits waiting humans, stages each active human's new position and
         launches one cycle (batched, or the per-human reference if plain)."""
         self._admit_waiting()
+        slots, xys = [], []
         for hid, xy in observations.items():
-            if hid in self.slot_of:
+            slot = self.slot_of.get(hid)
+            if slot is not None:
                 self._detect(hid, xy)
-                self.plan.stage(self.slot_of[hid], xy)
+                slots.append(slot)
+                xys.append(xy)
+        if slots:
+            self.plan.stage_many(slots, xys)   # one library call for all humans
         stream = self.streams[self.cycle % len(self.streams)]
         if self._dep is not None:
             for st in self.streams:

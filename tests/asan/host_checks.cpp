@@ -108,6 +108,10 @@ int main() {
     expect(plan == nullptr, "no plan returned on a device error");
   }
   cap_plan_destroy(nullptr);
+  const int32_t one_slot[1] = {0};
+  const float one_xy[2] = {0.f, 0.f};
+  expect_status(cap_plan_stage_obs_many(nullptr, 1, one_slot, one_xy), CAP_E_INVALID,
+                "staging without a plan");
 
   if (failures) std::fprintf(stderr, "%d host check(s) failed\n", failures);
   else std::printf("host checks passed\n");

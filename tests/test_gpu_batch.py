@@ -622,6 +622,29 @@ def test_plan_errors(cap):
     p.close()
 
 
+def test_stage_many_is_all_or_nothing(cap):
+    """Batched staging validates every entry before staging any: a call with
+    one bad entry leaves the good slots unstaged, so that the same positions
+    can be staged again."""
+    p = cap.Plan(16, 1.2, 0.02, 3, max_obs=1)
+    h = scenes.config3().humans[0]
+    bufs = [cap.SlotBuffers.allocate(cap.model_of(h), h.grid, 5, 2) for _ in range(2)]
+    p.admit(0, 1, cap.model_of(h), h.grid, 100, 5, h.start, bufs[0])
+    p.admit(1, 2, cap.model_of(h), h.grid, 100, 5, h.start, bufs[1])
+    with pytest.raises(cap.CapError):
+        p.stage_many([0, 2], [h.start, h.start])                       # slot 2 is empty
+    with pytest.raises(cap.CapError):
+        p.stage_many([0, 0], [h.start, h.start])                       # > max_obs for slot 0
+    with pytest.raises(cap.CapError):
+        p.stage_many([1, 0], [h.start, (float("nan"), 0.0)])           # bad position
+    p.stage_many([0, 1], [h.start, h.start])                           # nothing was staged before
+    with pytest.raises(cap.CapError):
+        p.stage(0, [h.start])                                          # now full
+    p.run(0, 0)
+    p.sync()
+    p.close()
+
+
 def test_replay_reproduces_the_cycle(orc, cap):
     """Re-running the latest rollout alone (the benchmark's kernel timing)
     recomputes the same grids: the clear covers both the previous and the new
