@@ -1,7 +1,8 @@
 // plan.hip -- batched many-human prediction: one persistent rollout launch per
-// cycle for every active human, captured with the belief update, the grid
-// clear and the normalisation in hipGraphs (one pair per ring entry), with
-// per-cycle descriptors refreshed by a single host-to-device copy.
+// cycle for every active human, captured with the grid clear and the
+// normalisation in a hipGraph per ring entry (and rollout variant), after the
+// belief update of every human in one launch, with per-cycle descriptors
+// refreshed by a single host-to-device copy.
 //
 // Scheduling: the particles of every human are cut into tiles of three sizes
 // (P, P/2 and P/4 particles per thread).  Each kind's tiles are dealt evenly
@@ -345,7 +346,6 @@ struct Entry {
   uint32_t* queues = nullptr;   // this entry's tile counter (device)
   uint8_t* dev = nullptr;       // header + slots
   uint8_t* host = nullptr;      // pinned mirror
-  hipGraphExec_t upd = nullptr;
   hipGraphExec_t main[2] = {nullptr, nullptr};  // [shift variant]
   hipEvent_t done = nullptr;
   bool pending = false;
@@ -442,13 +442,6 @@ static cap_status record_graphs(cap_plan* p, Entry& e) {
   hipStream_t s = p->cap_stream;
   hipGraph_t g = nullptr;
   const int minus1 = -1;
-  // belief update of every active slot
-  CAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  hipLaunchKernelGGL(plan_update_kernel, dim3(p->cfg.n_slots), dim3(kBeliefThreads), 0, s,
-                     (const uint8_t*)e.dev, minus1);
-  CAP_HIP(hipStreamEndCapture(s, &g));
-  CAP_HIP(hipGraphInstantiate(&e.upd, g, nullptr, nullptr, 0));
-  CAP_HIP(hipGraphDestroy(g));
   // clear -> persistent rollout -> normalise, once per rollout variant
   for (int v = 0; v < 2; ++v) {
     CAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -473,7 +466,6 @@ static cap_status record_graphs(cap_plan* p, Entry& e) {
 static void destroy_plan(cap_plan* p) {
   if (!p) return;
   for (auto& e : p->ring) {
-    if (e.upd) (void)hipGraphExecDestroy(e.upd);
     for (int v = 0; v < 2; ++v)
       if (e.main[v]) (void)hipGraphExecDestroy(e.main[v]);
     if (e.done) (void)hipEventDestroy(e.done);
@@ -945,7 +937,11 @@ extern "C" cap_status cap_plan_run(cap_plan* p, uint64_t seed, uint32_t cycle, v
   cap_status st = begin_cycle(p, seed, cycle, s, &e, &bytes);
   if (st != CAP_OK) return st;
   Entry& en = p->ring[e];
-  CAP_HIP(hipGraphLaunch(en.upd, s));
+  // the belief update is one kernel: launched directly (a one-node graph
+  // costs more host time), then its event, which the next cycle's stream waits on
+  hipLaunchKernelGGL(plan_update_kernel, dim3(p->cfg.n_slots), dim3(kBeliefThreads), 0, s,
+                     (const uint8_t*)en.dev, -1);
+  CAP_HIP(hipGetLastError());
   CAP_HIP(hipEventRecord(p->ev_update, s));
   CAP_HIP(hipGraphLaunch(en.main[p->last_variant], s));
   CAP_HIP(hipEventRecord(en.done, s));
