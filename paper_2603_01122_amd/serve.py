@@ -351,9 +351,12 @@ class Server:
 def run_paced(server, obs_fn, n_cycles: int, rate_hz: float = 125.0, progress=None,
               before_step=None, clock=time.perf_counter, sleep=time.sleep) -> np.ndarray:
     """Fixed-rate loop: cycle c is released at t0 + c/rate; between ticks the
-    host polls the completion events, every ~50 us while a cycle is in flight
-    (so that a completion is seen within about that) and every millisecond
-    otherwise.  before_step(c) (optional) runs after the release tick, before
+    host polls the completion events back to back while a cycle is in flight
+    (a completion is seen within one poll, a few microseconds; a sleep of
+    tens of microseconds would overshoot by the kernel's timer slack) and
+    sleeps otherwise, waking 150 us before the tick and spinning to it.  A
+    cycle that outlasts the period does not hold back the next tick's launch.
+    before_step(c) (optional) runs after the release tick, before
     the cycle is launched (arrivals and departures: their host work counts in
     that cycle's latency).  obs_fn(c) -> {hid: xy}.  Returns latencies (s);
     the server must stamp completions with the same clock."""
@@ -367,8 +370,8 @@ def run_paced(server, obs_fn, n_cycles: int, rate_hz: float = 125.0, progress=No
             now = clock()
             if now >= tick:
                 break
-            if tick - now > 200e-6:
-                sleep(min(tick - now - 150e-6, 50e-6 if pending else 1e-3))
+            if not pending and tick - now > 200e-6:
+                sleep(min(tick - now - 150e-6, 1e-3))
         if before_step is not None:
             before_step(c)
         recs.append(server.step(obs_fn(c), release=tick))

@@ -5,10 +5,10 @@
   is reused only after the in-flight work that uses it reports completion,
   departures of waiting humans;
 * deadline accounting -- run_paced releases cycle c at t0 + c / rate, a
-  cycle's latency is (completion seen by the host) - (release tick), polling
-  sees a completion within the poll interval, misses are latencies above the
-  period, and arrivals/departures run after the tick inside the cycle's
-  latency.
+  cycle's latency is (completion seen by the host) - (release tick), the
+  back-to-back polling while a cycle is in flight sees a completion within one
+  poll, misses are latencies above the period, and arrivals/departures run
+  after the tick inside the cycle's latency.
 """
 import collections
 import dataclasses
@@ -165,7 +165,11 @@ def test_paced_latency_and_misses_with_mock_clock():
         busy_wait = service[10] - period if c == 11 else 0.0
         finish = r.done_at - r.release
         assert 30e-6 + busy_wait + service[c] <= finish <= 30e-6 + busy_wait + service[c] + 10e-6
-        assert finish <= lat[c] <= finish + 60e-6, (c, lat[c], finish)
+        # while a cycle is in flight the loop polls back to back: the host
+        # sees the completion within one poll (two clock reads here); the last
+        # cycle completes in the final drain, which polls every 20 us
+        slack = 5e-6 if c < len(service) - 1 else 25e-6
+        assert finish <= lat[c] <= finish + slack, (c, lat[c], finish)
     s = latency_summary(lat, period)
     assert s["deadline_misses"] == 1 and s["cycles"] == 50
     assert abs(s["max_ms"] - lat.max() * 1e3) < 1e-3
