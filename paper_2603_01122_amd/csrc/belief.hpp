@@ -91,6 +91,47 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
   }
 }
 
+// policy_terms for a model of exactly KT controls (KT > 0): the same
+// operations in the same order (so the same bits), with the loops over the
+// controls unrolled -- the KT distance chains are independent, which the
+// runtime-length loops above hide from the scheduler -- and the chosen
+// control's Delta picked by a select in the loop instead of a dynamic index.
+template <int KT>
+__device__ __forceinline__ void policy_terms_fixed(const BeliefModel& m, float zx, float zy,
+                                                   int ks, float gx, float gy,
+                                                   const float* beta, int B, float* out) {
+  if (ks < 0) {
+    for (int b = 0; b < B; ++b) out[b] = 0.f;
+    return;
+  }
+  const float ax = zx - gx, bx = ax - zx;
+  const float ax_lo = (zx - (ax - bx)) + (-gx - bx);
+  const float ay = zy - gy, by = ay - zy;
+  const float ay_lo = (zy - (ay - by)) + (-gy - by);
+  const float D2 = fmaf(ax, ax, ay * ay);
+  const float D = sqrtf(D2);
+  const float ax2 = ax + ax, ay2 = ay + ay;
+  float dl[KT];
+  float dmin = INFINITY, dks = 0.f;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const float corr = fmaf(2.f * ax_lo, m.sx[k], fmaf(2.f * ay_lo, m.sy[k], m.s2[k]));
+    const float n = fmaf(ax2, m.sx[k], fmaf(ay2, m.sy[k], corr));
+    const float d = sqrtf(fmaxf(D2 + n, 0.f));
+    dl[k] = n / (d + D);
+    dmin = fminf(dmin, dl[k]);
+    dks = k == ks ? dl[k] : dks;
+  }
+  for (int b = 0; b < B; ++b) {
+    const float nbt = -beta[b];
+    const float mx = nbt * dmin;
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) s += exp_nonpos(nbt * dl[k] - mx);
+    out[b] = (nbt * dks - mx) - logf(s);
+  }
+}
+
 // Delta_u = |a + s_u| - |a| for a = z - g, the distance change of control u
 // that the policy's logits -beta Delta_u are built from (the shift-invariant
 // form of beta Q).  The posterior multiplies up to thousands of these terms

@@ -13,6 +13,7 @@ Bars (the accuracy targets of the prediction):
 * integer outputs (Philox words, normalisation bits, simulated lattices): exact.
 """
 import math
+import dataclasses
 import sys
 
 import numpy as np
@@ -210,8 +211,10 @@ def test_simulate_tracks_match_oracle(orc, cap):
     assert np.array_equal(p[same], pos_o[same])
 
 
-def _ll_inputs(orc, n=48, T=60, per_track=False, B=4, seed=0):
+def _ll_inputs(orc, n=48, T=60, per_track=False, B=4, seed=0, K=None):
     ts = scenes.config4(n_tracks=n, T=T)
+    if K is not None:
+        ts = dataclasses.replace(ts, K=K)
     _, pos = orc.simulate_tracks(K=ts.K, speed=ts.speed, dt=ts.dt, frame=ts.frame,
                                  start=ts.starts, beta=ts.true_beta, goal=ts.goals[ts.true_goal],
                                  T=ts.T, seed=seed)
@@ -247,6 +250,29 @@ def test_loglik_forward_backward_parity(orc, cap, per_track):
     dg2, db2 = cap.loglik_backward(ts.K, ts.speed, ts.dt, t(pos), t(lengths), t(goals), t(lb),
                                    t(dLL))
     assert np.array_equal(dg2.cpu().numpy(), dg) and np.array_equal(db2.cpu().numpy(), db)
+
+
+@pytest.mark.parametrize("K", [4, 6, 8, 16])
+def test_loglik_parity_other_headings(orc, cap, K):
+    """The forward and adjoint kernels are compiled for K in {4, 8, 16, 32}
+    and generic for any other K: each against the oracle on tracks simulated
+    with that K."""
+    ts, pos, lengths, goals, lb = _ll_inputs(orc, n=24, T=50, per_track=True, K=K)
+    note(f"loglik K={K}")
+    t = lambda a: torch.tensor(a, device="cuda")
+    LL = cap.loglik(ts.K, ts.speed, ts.dt, t(pos), t(lengths), t(goals), t(lb)).cpu().numpy()
+    kw = dict(K=ts.K, speed=ts.speed, dt=ts.dt, tracks=pos, lengths=lengths,
+              goals=goals.astype(np.float64), log_beta=lb.astype(np.float64),
+              per_track_beta=True)
+    LL_o = orc.loglik(**kw)
+    assert np.all(np.abs(LL - LL_o) <= 1e-5 * np.maximum(1.0, np.abs(LL_o)))
+    dLL = np.random.default_rng(2).normal(size=LL.shape)
+    dg, db = cap.loglik_backward(ts.K, ts.speed, ts.dt, t(pos), t(lengths), t(goals), t(lb),
+                                 t(dLL))
+    dg_o, db_o = orc.loglik_grad(dLL=dLL, **kw)
+    dg, db = dg.cpu().numpy(), db.cpu().numpy()
+    assert np.linalg.norm(dg - dg_o) <= 1e-5 * np.linalg.norm(dg_o)
+    assert np.linalg.norm(db - db_o) <= 1e-5 * np.linalg.norm(db_o)
 
 
 def test_autograd_function(orc, cap):
