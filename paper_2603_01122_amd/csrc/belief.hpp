@@ -91,11 +91,13 @@ __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, flo
   }
 }
 
-// policy_terms for a model of exactly KT controls (KT > 0): the same
-// operations in the same order (so the same bits), with the loops over the
-// controls unrolled -- the KT distance chains are independent, which the
-// runtime-length loops above hide from the scheduler -- and the chosen
-// control's Delta picked by a select in the loop instead of a dynamic index.
+// policy_terms for a model of exactly KT controls (KT > 0), for the batched
+// log-likelihood: the loops over the controls are unrolled (the KT distance
+// chains are independent, which the runtime-length loops above hide from the
+// scheduler), the chosen control's Delta is picked by a select in the loop
+// instead of a dynamic index, and the distances take the hardware square root
+// and reciprocal (within 1 ulp) in place of the IEEE ones: the log-likelihood's
+// error bar is 1e-5 of its magnitude, not the posterior's absolute 1e-5.
 template <int KT>
 __device__ __forceinline__ void policy_terms_fixed(const BeliefModel& m, float zx, float zy,
                                                    int ks, float gx, float gy,
@@ -109,7 +111,7 @@ __device__ __forceinline__ void policy_terms_fixed(const BeliefModel& m, float z
   const float ay = zy - gy, by = ay - zy;
   const float ay_lo = (zy - (ay - by)) + (-gy - by);
   const float D2 = fmaf(ax, ax, ay * ay);
-  const float D = sqrtf(D2);
+  const float D = fast_sqrt(D2);
   const float ax2 = ax + ax, ay2 = ay + ay;
   float dl[KT];
   float dmin = INFINITY, dks = 0.f;
@@ -117,8 +119,8 @@ __device__ __forceinline__ void policy_terms_fixed(const BeliefModel& m, float z
   for (int k = 0; k < KT; ++k) {
     const float corr = fmaf(2.f * ax_lo, m.sx[k], fmaf(2.f * ay_lo, m.sy[k], m.s2[k]));
     const float n = fmaf(ax2, m.sx[k], fmaf(ay2, m.sy[k], corr));
-    const float d = sqrtf(fmaxf(D2 + n, 0.f));
-    dl[k] = n / (d + D);
+    const float d = fast_sqrt(fmaxf(D2 + n, 0.f));
+    dl[k] = n * fast_rcp(d + D);
     dmin = fminf(dmin, dl[k]);
     dks = k == ks ? dl[k] : dks;
   }

@@ -96,14 +96,15 @@ __global__ void __launch_bounds__(kLLThreads)
     const float ay = zy - gy, by = ay - zy;
     const float ay_lo = (zy - (ay - by)) + (-gy - by);
     const float D2 = fmaf(ax, ax, ay * ay);
-    const float D = sqrtf(D2);
+    const float D = fast_sqrt(D2);
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
       if (KT == 0 && k >= K) break;
       const float corr = fmaf(2.f * ax_lo, a.m.sx[k], fmaf(2.f * ay_lo, a.m.sy[k], a.m.s2[k]));
       const float nk = fmaf(ax + ax, a.m.sx[k], fmaf(ay + ay, a.m.sy[k], corr));
-      dk[k] = sqrtf(fmaxf(D2 + nk, 0.f));
-      dl[k] = nk / (dk[k] + D);
+      // hardware square root and reciprocal, as in the forward's fixed-K path
+      dk[k] = fast_sqrt(fmaxf(D2 + nk, 0.f));
+      dl[k] = nk * fast_rcp(dk[k] + D);
     }
     if constexpr (KT > 0) {
       const float ds = dk[ks], dls = dl[ks], sxs = a.m.sx[ks], sys = a.m.sy[ks];
