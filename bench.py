@@ -235,8 +235,9 @@ def profiled_counters(best, scene="16humans"):
             h.update(f.read())
     shape = "block_threads=%s particles_per_thread=%s" % (
         best.get("block_threads"), best.get("particles_per_thread"))
-    if best.get("lds_bytes") is not None:
-        shape += " lds_bytes=%s" % best["lds_bytes"]
+    for extra in ("lds_bytes", "grid_blocks"):
+        if best.get(extra) is not None:
+            shape += " %s=%s" % (extra, best[extra])
     if h.hexdigest() != fields["source_sha256"].strip() or shape != fields[pre + "tuning"].strip():
         return None
     return {"traffic": int(fields[pre + "traffic_bytes_per_launch"]),
