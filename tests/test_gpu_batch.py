@@ -75,7 +75,9 @@ def snapshot(srv, hid, c):
 
 
 @pytest.mark.parametrize("shape", [{}, dict(block_threads=256, particles_per_thread=4),
-                                   dict(block_threads=512, particles_per_thread=2)])
+                                   dict(block_threads=512, particles_per_thread=2),
+                                   dict(block_threads=256, particles_per_thread=4,
+                                        lds_bytes=24576, grid_blocks=768)])
 def test_batched_equals_plain_and_single(orc, cap, shape):
     """Batched, per-human and single-human launches give the same bits.  With
     an even number of particles per thread the K = 16 rollout draws two
