@@ -258,15 +258,13 @@ class Server:
         """Admits waiting humans, stages each active human's new position and
         launches one cycle (batched, or the per-human reference if plain)."""
         self._admit_waiting()
-        slots, xys = [], []
-        for hid, xy in observations.items():
-            slot = self.slot_of.get(hid)
-            if slot is not None:
-                self._detect(hid, xy)
-                slots.append(slot)
-                xys.append(xy)
-        if slots:
-            self.plan.stage_many(slots, xys)   # one library call for all humans
+        seen = [(hid, xy) for hid, xy in observations.items() if hid in self.slot_of]
+        if seen:
+            # one library call for all humans, validated as a whole: a rejected
+            # observation leaves every human's state as it was
+            self.plan.stage_many([self.slot_of[hid] for hid, _ in seen], [xy for _, xy in seen])
+        for hid, xy in seen:
+            self._detect(hid, xy)
         stream = self.streams[self.cycle % len(self.streams)]
         if self._dep is not None:
             for st in self.streams:
