@@ -30,6 +30,7 @@ constexpr int kMaxObs = 8;
 constexpr int kXcds = 8;
 constexpr int kQueueWords = kXcds;   // tile counters per ring entry, one per XCD
 constexpr int kTileKinds = 3;    // P, P/2, P/4 particles per thread
+constexpr int kZeroBlocks = 2048;  // blocks of the grid clear
 
 struct SlotDev {
   RolloutDesc rd;          // rollout of this cycle (start, ring-entry outputs)
@@ -81,11 +82,10 @@ __device__ __forceinline__ const SlotDev* slots_of(const uint8_t* base) {
 }
 
 // ---------------------------------------------------------------- kernels
-__global__ void __launch_bounds__(kBeliefThreads)
-    plan_update_kernel(const uint8_t* __restrict__ base, int only) {
-  __shared__ BeliefShared sh;
+// Belief update of slot s (one block).
+__device__ __forceinline__ void update_slot(const uint8_t* __restrict__ base, int s,
+                                            BeliefShared& sh) {
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
-  const int s = only >= 0 ? only : (int)blockIdx.x;
   if (s >= H->n_active) return;
   const SlotDev& sd = slots_of(base)[s];
   const int J = sd.bm.G * sd.bm.B;
@@ -95,6 +95,12 @@ __global__ void __launch_bounds__(kBeliefThreads)
   }
   belief_update_block(sd.bm, sd.obs, sd.n_obs, sd.log_belief, const_cast<double*>(sd.rd.belief),
                       sh);
+}
+
+__global__ void __launch_bounds__(kBeliefThreads)
+    plan_update_kernel(const uint8_t* __restrict__ base, int only) {
+  __shared__ BeliefShared sh;
+  update_slot(base, only >= 0 ? only : (int)blockIdx.x, sh);
 }
 
 // Clearing and normalising work only where a ring entry's grids can be
@@ -135,14 +141,16 @@ __device__ __forceinline__ void item_range(const CycleHeader* H, int only, int* 
 
 // Clears the counts (and off-grid counters) of every active slot (only < 0) --
 // or of slot `only` -- and resets the tile queues for the rollout that follows.
-__global__ void __launch_bounds__(256)
-    plan_zero_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int only) {
+// Block `blk` of `nblk` of the clear (see plan_zero_kernel).
+__device__ __forceinline__ void zero_items(const uint8_t* __restrict__ base,
+                                           uint32_t* __restrict__ queues, int only, int blk,
+                                           int nblk) {
   const CycleHeader* H = reinterpret_cast<const CycleHeader*>(base);
-  if (blockIdx.x == 0 && threadIdx.x < kQueueWords) queues[threadIdx.x] = 0u;
+  if (blk == 0 && threadIdx.x < kQueueWords) queues[threadIdx.x] = 0u;
   const SlotDev* sl = slots_of(base);
   int i0, i1;
   item_range(H, only, &i0, &i1);
-  for (int it = i0 + (int)blockIdx.x; it < i1; it += (int)gridDim.x) {
+  for (int it = i0 + blk; it < i1; it += nblk) {
     const int s = __builtin_amdgcn_readfirstlane(slot_of_step(H, it));
     const SlotDev& sd = sl[s];
     const int t = it - H->step_begin[s] + 1;
@@ -160,10 +168,29 @@ __global__ void __launch_bounds__(256)
   if (H->union_out && (only == -1 || only == 0)) {
     const size_t n = (size_t)H->union_H * H->union_nx * H->union_ny;
     global_ptr<uint32_t> u = as_global(reinterpret_cast<uint32_t*>(H->union_out));
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
+    for (size_t i = (size_t)blk * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)nblk * blockDim.x)
       u[i] = 0u;
   }
+}
+
+__global__ void __launch_bounds__(256)
+    plan_zero_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues, int only) {
+  zero_items(base, queues, only, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// The start of a batched cycle in one launch: blocks [0, n_slots) update the
+// beliefs (one per slot), the rest clear the grids and reset the tile queues.
+// The two are independent, so they run side by side instead of one after the
+// other (and one launch gap fewer).
+__global__ void __launch_bounds__(kBeliefThreads)
+    plan_prelude_kernel(const uint8_t* __restrict__ base, uint32_t* __restrict__ queues,
+                        int n_slots) {
+  __shared__ BeliefShared sh;
+  if ((int)blockIdx.x < n_slots)
+    update_slot(base, (int)blockIdx.x, sh);
+  else
+    zero_items(base, queues, -1, (int)blockIdx.x - n_slots, (int)gridDim.x - n_slots);
 }
 
 __global__ void __launch_bounds__(256)
@@ -442,11 +469,10 @@ static cap_status record_graphs(cap_plan* p, Entry& e) {
   hipStream_t s = p->cap_stream;
   hipGraph_t g = nullptr;
   const int minus1 = -1;
-  // clear -> persistent rollout -> normalise, once per rollout variant
+  // persistent rollout -> normalise, once per rollout variant (the clear runs
+  // in the prelude launch before it)
   for (int v = 0; v < 2; ++v) {
     CAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipLaunchKernelGGL(plan_zero_kernel, dim3(2048), dim3(256), 0, s, (const uint8_t*)e.dev,
-                       e.queues, minus1);
     cap_status st = launch_rollout(p, e, v, s);
     hipLaunchKernelGGL(plan_normalize_kernel, dim3(4096), dim3(256), 0, s, (const uint8_t*)e.dev,
                        minus1);
@@ -937,10 +963,10 @@ extern "C" cap_status cap_plan_run(cap_plan* p, uint64_t seed, uint32_t cycle, v
   cap_status st = begin_cycle(p, seed, cycle, s, &e, &bytes);
   if (st != CAP_OK) return st;
   Entry& en = p->ring[e];
-  // the belief update is one kernel: launched directly (a one-node graph
+  // belief update and grid clear in one direct launch (a graph of one node
   // costs more host time), then its event, which the next cycle's stream waits on
-  hipLaunchKernelGGL(plan_update_kernel, dim3(p->cfg.n_slots), dim3(kBeliefThreads), 0, s,
-                     (const uint8_t*)en.dev, -1);
+  hipLaunchKernelGGL(plan_prelude_kernel, dim3(p->cfg.n_slots + kZeroBlocks), dim3(kBeliefThreads),
+                     0, s, (const uint8_t*)en.dev, en.queues, p->cfg.n_slots);
   CAP_HIP(hipGetLastError());
   CAP_HIP(hipEventRecord(p->ev_update, s));
   CAP_HIP(hipGraphLaunch(en.main[p->last_variant], s));
@@ -999,7 +1025,7 @@ extern "C" cap_status cap_plan_replay_rollout(cap_plan* p, void* stream, void* e
   hipStream_t s = as_stream(stream);
   const Entry& en = p->ring[p->last_run_entry];
   const int replay = -2;  // every slot, union grid untouched
-  hipLaunchKernelGGL(plan_zero_kernel, dim3(2048), dim3(256), 0, s, (const uint8_t*)en.dev,
+  hipLaunchKernelGGL(plan_zero_kernel, dim3(kZeroBlocks), dim3(256), 0, s, (const uint8_t*)en.dev,
                      en.queues, replay);
   if (ev_start) CAP_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(ev_start), s));
   cap_status st = launch_rollout(p, en, p->last_variant, s);
