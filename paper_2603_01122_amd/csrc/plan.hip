@@ -1,7 +1,7 @@
 // plan.hip -- batched many-human prediction: one persistent rollout launch per
-// cycle for every active human, captured with the grid clear and the
-// normalisation in a hipGraph per ring entry (and rollout variant), after the
-// belief update of every human in one launch, with per-cycle descriptors
+// cycle for every active human, captured with the normalisation in a hipGraph
+// per ring entry (and rollout variant), after one prelude launch that updates
+// every human's belief and clears the grids, with per-cycle descriptors
 // refreshed by a single host-to-device copy.
 //
 // Scheduling: the particles of every human are cut into tiles of three sizes
