@@ -1,22 +1,46 @@
 // loglik.hip -- batched trajectory log-likelihood (product form of
 // Eq. beta_update over each track) and its adjoint with respect to the goal
-// positions and log beta.  One wavefront per (track, goal): lanes take
-// observed steps, FP32 policy terms are accumulated per lane in FP64 and
-// reduced across the wave by a fixed butterfly, so results are bitwise
-// reproducible.  The adjoint writes per-(track, goal) partials to the
+// positions and log beta.  A wavefront takes 64 / L goals of one track, and
+// each goal's L lanes stride over the observed steps (L = 64: one goal per
+// wave).  FP32 policy terms are accumulated per lane in FP64 and reduced
+// across each goal's lanes by a fixed butterfly, so for a given L results are
+// bitwise reproducible.  The adjoint writes per-(track, goal) partials to the
 // workspace and a second kernel sums them in a fixed order (no atomics).
+#include <algorithm>
 #include <mutex>
 
 #include "belief.hpp"
 
 namespace capred {
 
-constexpr int kLLThreads = 256;  // 4 wavefronts, each one (track, goal)
+constexpr int kLLThreads = 256;  // 4 wavefronts
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Sum over the 2^lg lanes of this lane's goal (a butterfly inside the group).
+__device__ __forceinline__ double group_sum(double v, int lg) {
+  for (int o = (1 << lg) >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// This lane's (track, goal, first step) for 2^lg lanes per goal; `on` is false
+// for the lanes of a wave's last goal slots beyond G (they add nothing but
+// take part in the group sums).
+struct LLItem {
+  int n, g, sub;
+  bool on;
+};
+
+__device__ __forceinline__ bool ll_item(int G, int N, int lg, LLItem* it) {
+  const int lane = threadIdx.x & 63;
+  const int gpw = 64 >> lg;                    // goals per wave
+  const int groups = (G + gpw - 1) / gpw;      // waves per track
+  const int wave = blockIdx.x * (kLLThreads / 64) + (threadIdx.x >> 6);
+  if (wave >= N * groups) return false;        // whole wavefront exits together
+  it->n = wave / groups;
+  const int g = (wave - it->n * groups) * gpw + (lane >> lg);
+  it->on = g < G;
+  it->g = it->on ? g : 0;
+  it->sub = lane & ((1 << lg) - 1);
+  return true;
 }
 
 struct LLArgs {
@@ -34,19 +58,19 @@ __device__ __forceinline__ void load_beta(const LLArgs& a, int n, float* beta) {
 }
 
 template <int KT>
-__global__ void __launch_bounds__(kLLThreads) loglik_kernel(const LLArgs a, double* __restrict__ LL) {
-  const int lane = threadIdx.x & 63;
-  const int item = blockIdx.x * (kLLThreads / 64) + (threadIdx.x >> 6);
-  if (item >= a.N * a.G) return;  // whole wavefront exits together
-  const int n = item / a.G, g = item - n * a.G;
-  const int len = a.lengths[n];
+__global__ void __launch_bounds__(kLLThreads)
+    loglik_kernel(const LLArgs a, int lg, double* __restrict__ LL) {
+  LLItem it;
+  if (!ll_item(a.G, a.N, lg, &it)) return;
+  const int n = it.n, g = it.g;
+  const int len = it.on ? a.lengths[n] : 0;
   const float* z = a.tracks + (size_t)n * (a.Tmax + 1) * 2;
   const float gx = a.goals[2 * g], gy = a.goals[2 * g + 1];
   float beta[CAP_MAX_B], terms[CAP_MAX_B];
   load_beta(a, n, beta);
   double acc[CAP_MAX_B];
   for (int b = 0; b < a.B; ++b) acc[b] = 0.0;
-  for (int t = lane; t < len; t += 64) {
+  for (int t = it.sub; t < len; t += 1 << lg) {
     const float zx = z[2 * t], zy = z[2 * t + 1];
     const int ks = recover_control(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
     if constexpr (KT > 0)
@@ -56,8 +80,8 @@ __global__ void __launch_bounds__(kLLThreads) loglik_kernel(const LLArgs a, doub
     for (int b = 0; b < a.B; ++b) acc[b] += (double)terms[b];
   }
   for (int b = 0; b < a.B; ++b) {
-    const double s = wave_sum(acc[b]);
-    if (lane == 0) LL[((size_t)n * a.B + b) * a.G + g] = s;
+    const double s = group_sum(acc[b], lg);
+    if (it.on && it.sub == 0) LL[((size_t)n * a.B + b) * a.G + g] = s;
   }
 }
 
@@ -70,14 +94,13 @@ __global__ void __launch_bounds__(kLLThreads) loglik_kernel(const LLArgs a, doub
 // the per-heading arrays stay in registers); KT == 0: any K.
 template <int KT>
 __global__ void __launch_bounds__(kLLThreads)
-    loglik_backward_kernel(const LLArgs a, const double* __restrict__ dLL,
+    loglik_backward_kernel(const LLArgs a, int lg, const double* __restrict__ dLL,
                            double* __restrict__ ws_g, double* __restrict__ ws_b) {
   constexpr int KM = KT > 0 ? KT : CAP_MAX_K;
-  const int lane = threadIdx.x & 63;
-  const int item = blockIdx.x * (kLLThreads / 64) + (threadIdx.x >> 6);
-  if (item >= a.N * a.G) return;
-  const int n = item / a.G, g = item - n * a.G;
-  const int len = a.lengths[n];
+  LLItem it;
+  if (!ll_item(a.G, a.N, lg, &it)) return;
+  const int n = it.n, g = it.g;
+  const int len = it.on ? a.lengths[n] : 0;
   const int K = KT > 0 ? KT : a.m.K, B = a.B;
   const float* z = a.tracks + (size_t)n * (a.Tmax + 1) * 2;
   const float gx = a.goals[2 * g], gy = a.goals[2 * g + 1];
@@ -87,7 +110,7 @@ __global__ void __launch_bounds__(kLLThreads)
   double agx = 0.0, agy = 0.0, ab[CAP_MAX_B];
   for (int b = 0; b < B; ++b) ab[b] = 0.0;
   float dl[KM], dk[KM];
-  for (int t = lane; t < len; t += 64) {
+  for (int t = it.sub; t < len; t += 1 << lg) {
     const float zx = z[2 * t], zy = z[2 * t + 1];
     const int ks = recover_control(a.m, z[2 * t + 2] - zx, z[2 * t + 3] - zy);
     if (ks < 0) continue;
@@ -194,14 +217,14 @@ __global__ void __launch_bounds__(kLLThreads)
       }
     }
   }
-  const double sgx = wave_sum(agx), sgy = wave_sum(agy);
-  if (lane == 0) {
+  const double sgx = group_sum(agx, lg), sgy = group_sum(agy, lg);
+  if (it.on && it.sub == 0) {
     ws_g[((size_t)n * a.G + g) * 2] = sgx;
     ws_g[((size_t)n * a.G + g) * 2 + 1] = sgy;
   }
   for (int b = 0; b < B; ++b) {
-    const double s = wave_sum(ab[b]);
-    if (lane == 0) ws_b[((size_t)n * a.G + g) * B + b] = s;
+    const double s = group_sum(ab[b], lg);
+    if (it.on && it.sub == 0) ws_b[((size_t)n * a.G + g) * B + b] = s;
   }
 }
 
@@ -249,6 +272,37 @@ __global__ void loglik_track_beta_kernel(int N, int G, int B, const double* __re
   dlog_beta[jb] = s;
 }
 
+// log2 of the lanes per (track, goal) for a launch.  Fewer lanes per goal
+// leave fewer idle in a track's last pass over its steps (200 steps: 78 % of
+// the lanes busy at 64 lanes per goal, 89 % at 32, 96 % at 16) but make fewer
+// waves.  Each width is scored by its busy fraction (from Tmax, and the goal
+// slots the last wave of a track leaves empty) times the fraction of
+// `target_waves` resident wave slots its waves fill; ties keep the wider form.
+static int ll_lanes_log2(int N, int G, int Tmax, double target_waves) {
+  int best = 6;
+  double best_score = -1.0;
+  for (int lg = 6; lg >= 3; --lg) {
+    const int L = 1 << lg, gpw = 64 >> lg;
+    const long groups = (G + gpw - 1) / gpw;
+    const double waves = (double)N * (double)groups;
+    const double passes = Tmax > 0 ? (double)((Tmax + L - 1) / L) : 1.0;
+    const double busy = (Tmax > 0 ? Tmax / (L * passes) : 1.0) * ((double)G / ((double)groups * gpw));
+    const double score = busy * std::min(1.0, waves / target_waves);
+    if (score > best_score + 1e-9) {
+      best = lg;
+      best_score = score;
+    }
+  }
+  return best;
+}
+
+// Resident wave slots of the device's 1024 SIMDs (256 CUs x 4) at each
+// kernel's occupancy: the forward holds four waves per SIMD at every K; the
+// adjoint two at K = 32 (247 VGPRs), three at K = 16, four below.
+constexpr double kSimds = 1024.0;
+static double ll_forward_waves() { return 4.0 * kSimds; }
+static double ll_backward_waves(int K) { return (K > 16 || K == 0 ? 2.0 : K > 8 ? 3.0 : 4.0) * kSimds; }
+
 static cap_status make_ll_args(int32_t K, double speed, double dt, const float* tracks,
                                const int32_t* lengths, int32_t N, int32_t Tmax,
                                const float* goals, int32_t G, const float* log_beta, int32_t B,
@@ -288,15 +342,17 @@ extern "C" cap_status cap_loglik(int32_t K, double speed, double dt, const float
   if (st != CAP_OK) return st;
   if (N == 0) return CAP_OK;
   if (!LL_dev) return fail(CAP_E_INVALID, "LL is NULL");
-  const int items = N * G, per_block = kLLThreads / 64;
-  const dim3 grid((items + per_block - 1) / per_block), block(kLLThreads);
+  const int lg = ll_lanes_log2(N, G, Tmax, ll_forward_waves());
+  const int gpw = 64 >> lg, per_block = kLLThreads / 64;
+  const long waves = (long)N * ((G + gpw - 1) / gpw);
+  const dim3 grid((unsigned)((waves + per_block - 1) / per_block)), block(kLLThreads);
   hipStream_t s = as_stream(stream);
   switch (a.m.U) {
-    case 4: hipLaunchKernelGGL(loglik_kernel<4>, grid, block, 0, s, a, LL_dev); break;
-    case 8: hipLaunchKernelGGL(loglik_kernel<8>, grid, block, 0, s, a, LL_dev); break;
-    case 16: hipLaunchKernelGGL(loglik_kernel<16>, grid, block, 0, s, a, LL_dev); break;
-    case 32: hipLaunchKernelGGL(loglik_kernel<32>, grid, block, 0, s, a, LL_dev); break;
-    default: hipLaunchKernelGGL(loglik_kernel<0>, grid, block, 0, s, a, LL_dev); break;
+    case 4: hipLaunchKernelGGL(loglik_kernel<4>, grid, block, 0, s, a, lg, LL_dev); break;
+    case 8: hipLaunchKernelGGL(loglik_kernel<8>, grid, block, 0, s, a, lg, LL_dev); break;
+    case 16: hipLaunchKernelGGL(loglik_kernel<16>, grid, block, 0, s, a, lg, LL_dev); break;
+    case 32: hipLaunchKernelGGL(loglik_kernel<32>, grid, block, 0, s, a, lg, LL_dev); break;
+    default: hipLaunchKernelGGL(loglik_kernel<0>, grid, block, 0, s, a, lg, LL_dev); break;
   }
   CAP_HIP(hipGetLastError());
   return CAP_OK;
@@ -319,14 +375,17 @@ static cap_status loglik_backward_launch(const LLArgs& a, int32_t per_track_beta
   double* ws_g = static_cast<double*>(ws_dev);
   double* ws_b = ws_g + (size_t)N * G * 2;
   if (N > 0) {
-    const int items = N * G, per_block = kLLThreads / 64;
-    const dim3 grid((items + per_block - 1) / per_block), block(kLLThreads);
-    switch (a.m.K) {
-      case 4: hipLaunchKernelGGL(loglik_backward_kernel<4>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
-      case 8: hipLaunchKernelGGL(loglik_backward_kernel<8>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
-      case 16: hipLaunchKernelGGL(loglik_backward_kernel<16>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
-      case 32: hipLaunchKernelGGL(loglik_backward_kernel<32>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
-      default: hipLaunchKernelGGL(loglik_backward_kernel<0>, grid, block, 0, s, a, dLL_dev, ws_g, ws_b); break;
+    const int kt = a.m.K == 4 || a.m.K == 8 || a.m.K == 16 || a.m.K == 32 ? a.m.K : 0;
+    const int lg = ll_lanes_log2(N, G, a.Tmax, ll_backward_waves(kt));
+    const int gpw = 64 >> lg, per_block = kLLThreads / 64;
+    const long waves = (long)N * ((G + gpw - 1) / gpw);
+    const dim3 grid((unsigned)((waves + per_block - 1) / per_block)), block(kLLThreads);
+    switch (kt) {
+      case 4: hipLaunchKernelGGL(loglik_backward_kernel<4>, grid, block, 0, s, a, lg, dLL_dev, ws_g, ws_b); break;
+      case 8: hipLaunchKernelGGL(loglik_backward_kernel<8>, grid, block, 0, s, a, lg, dLL_dev, ws_g, ws_b); break;
+      case 16: hipLaunchKernelGGL(loglik_backward_kernel<16>, grid, block, 0, s, a, lg, dLL_dev, ws_g, ws_b); break;
+      case 32: hipLaunchKernelGGL(loglik_backward_kernel<32>, grid, block, 0, s, a, lg, dLL_dev, ws_g, ws_b); break;
+      default: hipLaunchKernelGGL(loglik_backward_kernel<0>, grid, block, 0, s, a, lg, dLL_dev, ws_g, ws_b); break;
     }
     CAP_HIP(hipGetLastError());
   }

@@ -73,6 +73,43 @@ def test_full_size_forward_sampled_and_backward(orc, cap, tracks):
     assert np.linalg.norm(db - db_o) <= 1e-5 * np.linalg.norm(db_o)
 
 
+def test_goals_packed_per_wave_ragged_lengths(orc, cap):
+    """2048 tracks of up to 150 steps (ragged, including empty and one-step
+    tracks), 7 goals, K = 32, 9 beta.  At this size the library packs several
+    goals into one wave (forward: 2 goals of 32 lanes; adjoint: 8 goals of 8
+    lanes), so the last wave of each track leaves one goal slot empty and
+    each goal's lanes end their steps at different passes."""
+    ts = scenes.config4(n_tracks=2048, T=150)
+    _, pos = orc.simulate_tracks(K=ts.K, speed=ts.speed, dt=ts.dt, frame=ts.frame,
+                                 start=ts.starts, beta=ts.true_beta, goal=ts.goals[ts.true_goal],
+                                 T=ts.T, seed=1)
+    n = pos.shape[0]
+    r = np.random.default_rng(5)
+    lengths = r.integers(0, ts.T + 1, size=n).astype(np.int32)
+    lengths[:4] = [0, 1, ts.T, 2]
+    goals = (ts.goals[:7] + r.normal(scale=0.2, size=(7, 2))).astype(np.float32)
+    log_beta = np.log(ts.beta_grid).astype(np.float32)
+    t = lambda a: torch.tensor(a, device="cuda")
+    note("loglik 2048 x <=150 ragged, K=32, 7 goals, 9 beta")
+    LL = cap.loglik(ts.K, ts.speed, ts.dt, t(pos), t(lengths), t(goals), t(log_beta))
+    torch.cuda.synchronize()
+    LL = LL.cpu().numpy()
+    idx = np.sort(np.concatenate([np.arange(4), r.choice(np.arange(4, n), 124, replace=False)]))
+    kw = dict(K=ts.K, speed=ts.speed, dt=ts.dt, goals=goals.astype(np.float64),
+              log_beta=log_beta.astype(np.float64))
+    LL_o = orc.loglik(tracks=pos[idx], lengths=lengths[idx], **kw)
+    assert np.all(np.abs(LL[idx] - LL_o) <= 1e-5 * np.maximum(1.0, np.abs(LL_o)))
+    assert np.all(LL[0] == 0.0)
+    dLL = r.normal(size=LL.shape)
+    note("loglik backward 2048 x <=150 ragged, 7 goals")
+    dg, db = cap.loglik_backward(ts.K, ts.speed, ts.dt, t(pos), t(lengths), t(goals),
+                                 t(log_beta), t(dLL))
+    dg_o, db_o = orc.loglik_grad(tracks=pos, lengths=lengths, dLL=dLL, **kw)
+    dg, db = dg.cpu().numpy(), db.cpu().numpy()
+    assert np.linalg.norm(dg - dg_o) <= 1e-5 * np.linalg.norm(dg_o)
+    assert np.linalg.norm(db - db_o) <= 1e-5 * np.linalg.norm(db_o)
+
+
 def _fit_gpu(cap, ts, pos, lengths, goals0, lb0, iters, lr):
     from paper_2603_01122_amd.fit import fit_goals_beta
     t = lambda a: torch.tensor(a, device="cuda")
