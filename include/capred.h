@@ -200,7 +200,10 @@ cap_status cap_simulate_tracks(int32_t K, double speed, int32_t n_speeds, const 
  *   goals_dev    [G][2] FP32 metres (continuous, differentiable).
  *   log_beta_dev [B] FP32, or [N][B] when per_track_beta != 0.
  *   LL_dev       [N][B][G] FP64 out.
- * FP32 policy terms, FP64 sums over t.  No workspace. */
+ * FP32 policy terms, FP64 sums over t.  No workspace.
+ * CAP_E_INVALID (nothing launched) for a bad K, speed or dt, N < 0, Tmax < 0,
+ * G outside [1, CAP_MAX_G], B outside [1, CAP_MAX_B], N * G above 2^25, or a
+ * NULL pointer with N > 0; N = 0 writes nothing. */
 cap_status cap_loglik(int32_t K, double speed, double dt, const float* tracks_dev,
                       const int32_t* lengths_dev, int32_t N, int32_t Tmax,
                       const float* goals_dev, int32_t G, const float* log_beta_dev, int32_t B,

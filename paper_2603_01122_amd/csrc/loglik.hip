@@ -313,6 +313,8 @@ static cap_status make_ll_args(int32_t K, double speed, double dt, const float* 
   if (N < 0 || Tmax < 0) return fail(CAP_E_INVALID, "N and Tmax must be >= 0");
   if (G < 1 || G > CAP_MAX_G || B < 1 || B > CAP_MAX_B)
     return fail(CAP_E_INVALID, "G in [1, 64] and B in [1, 16] required");
+  // one wave (64 threads) per (track, goal) at most: thread indices stay in int
+  if ((int64_t)N * G > ((int64_t)1 << 25)) return fail(CAP_E_INVALID, "N * G above 2^25");
   if (N > 0 && (!tracks || !lengths || !goals || !log_beta))
     return fail(CAP_E_INVALID, "tracks/lengths/goals/log_beta is NULL");
   a->m = make_belief_model(c, dt, 0, nullptr, 0, nullptr);

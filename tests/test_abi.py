@@ -106,6 +106,11 @@ def test_invalid_loglik_and_workspace(cap):
     assert rc == cap.CAP_E_INVALID
     rc = cap._lib.cap_loglik(1, 1.0, 0.1, p, p, 10, 5, p, 3, p, 4, 0, p, None)
     assert rc == cap.CAP_E_INVALID
+    # N * G above 2^25 (one wave per (track, goal) at most must keep int thread indices)
+    rc = cap._lib.cap_loglik(8, 1.0, 0.1, p, p, (1 << 22) + 1, 5, p, 8, p, 4, 0, p, None)
+    assert rc == cap.CAP_E_INVALID and b"2^25" in cap._lib.cap_last_error()
+    rc = f(8, 1.0, 0.1, p, p, (1 << 22) + 1, 5, p, 8, p, 4, 0, p, p, p, p, 1 << 40, None)
+    assert rc == cap.CAP_E_INVALID
     rc = cap._lib.cap_normalize(p, 10, 0, p, None)
     assert rc == cap.CAP_E_INVALID
     rc = cap._lib.cap_philox_blocks(-1, 0, 0, 0, 0, 0, p, None)
