@@ -298,10 +298,13 @@ static int ll_lanes_log2(int N, int G, int Tmax, double target_waves) {
 
 // Resident wave slots of the device's 1024 SIMDs (256 CUs x 4) at each
 // kernel's occupancy: the forward holds four waves per SIMD at every K; the
-// adjoint two at K = 32 (247 VGPRs), three at K = 16, four below.
+// adjoint two at K = 32 (247 VGPRs), three at K = 16 and in the any-K build
+// (kt = 0), four at K <= 8.
 constexpr double kSimds = 1024.0;
 static double ll_forward_waves() { return 4.0 * kSimds; }
-static double ll_backward_waves(int K) { return (K > 16 || K == 0 ? 2.0 : K > 8 ? 3.0 : 4.0) * kSimds; }
+static double ll_backward_waves(int kt) {
+  return (kt == 32 ? 2.0 : kt == 16 || kt == 0 ? 3.0 : 4.0) * kSimds;
+}
 
 static cap_status make_ll_args(int32_t K, double speed, double dt, const float* tracks,
                                const int32_t* lengths, int32_t N, int32_t Tmax,
