@@ -56,6 +56,11 @@ __device__ __forceinline__ int recover_control(const BeliefModel& m, float dx, f
 // 2e-7 + |x| 6e-8, against 1e-5 for the posterior and log-likelihood bars.
 __device__ __forceinline__ float exp_nonpos(float x) { return fast_exp2(x * kLog2e); }
 
+// Hardware base-2 logarithm (within 1 ulp for the normal arguments it gets
+// here: sums of K weights whose largest is 1).
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+constexpr float kLn2 = 0.6931471805599453f;
+
 template <int NMAX>
 __device__ __forceinline__ void policy_terms(const BeliefModel& m, float zx, float zy, int ks,
                                              float gx, float gy, const float* beta, int B,
@@ -124,13 +129,16 @@ __device__ __forceinline__ void policy_terms_fixed(const BeliefModel& m, float z
     dmin = fminf(dmin, dl[k]);
     dks = k == ks ? dl[k] : dks;
   }
+  // logits in base 2: a_k = -beta log2(e) Delta_k - c with the shift c = -beta
+  // log2(e) min_k Delta_k (rounded), so pi_k = 2^a_k / sum_j 2^a_j for any c
+  // and the term is (a_k* - log2 sum_j 2^a_j) ln 2; each exponent is one FMA
   for (int b = 0; b < B; ++b) {
-    const float nbt = -beta[b];
-    const float mx = nbt * dmin;
+    const float nb2 = -beta[b] * kLog2e;
+    const float mx2 = nb2 * dmin;
     float s = 0.f;
 #pragma unroll
-    for (int k = 0; k < KT; ++k) s += exp_nonpos(nbt * dl[k] - mx);
-    out[b] = (nbt * dks - mx) - logf(s);
+    for (int k = 0; k < KT; ++k) s += fast_exp2(fmaf(nb2, dl[k], -mx2));
+    out[b] = (fmaf(nb2, dks, -mx2) - fast_log2(s)) * kLn2;
   }
 }
 

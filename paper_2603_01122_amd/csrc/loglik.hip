@@ -162,11 +162,13 @@ __global__ void __launch_bounds__(kLLThreads)
       }
       for (int b = 0; b < B; ++b) {
         const float nbt = -beta[b];
-        const float mx = nbt * dmin;
+        // base-2 exponents with the shift folded into one FMA (p is a ratio,
+        // so the shift's rounding cancels)
+        const float nb2 = nbt * kLog2e, mx2 = nb2 * dmin;
         float s = 0.f, ex = 0.f, ey = 0.f, ed = 0.f;
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
-            const float p = exp_nonpos(nbt * dl[k] - mx);
+          const float p = fast_exp2(fmaf(nb2, dl[k], -mx2));
           s += p;
           ex = fmaf(p, ux[k], ex);
           ey = fmaf(p, uy[k], ey);
