@@ -199,7 +199,16 @@ __global__ void __launch_bounds__(256)
   const SlotDev* sl = slots_of(base);
   int i0, i1;
   item_range(H, only, &i0, &i1);
-  for (int it = i0 + (int)blockIdx.x; it < i1; it += (int)gridDim.x) {
+  const int items = i1 - i0;
+  if (items <= 0) return;
+  // A (slot, step) item takes `per` blocks when the grid has room, its rows
+  // dealt round-robin to their waves: with one block per item each wave
+  // walks tens of rows of a late step's window, one dependent load and store
+  // after another.
+  const int per = max(1, (int)gridDim.x / items);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int u = (int)blockIdx.x; u < items * per; u += (int)gridDim.x) {
+    const int it = i0 + u / per, band = u - (u / per) * per;
     const int s = __builtin_amdgcn_readfirstlane(slot_of_step(H, it));
     const SlotDev& sd = sl[s];
     if (!sd.probs || sd.smooth_r > 0) continue;
@@ -211,8 +220,7 @@ __global__ void __launch_bounds__(256)
     const float N = (float)sd.rd.N;
     const bool un = sd.in_union != 0;
     const size_t corner = (size_t)r.y0 * sd.rd.nx + r.x0;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int y = wave; y < r.h; y += nw)
+    for (int y = band * nw + wave; y < r.h; y += per * nw)
       for (int x = lane; x < r.w; x += 64) {
         const size_t c = (size_t)y * sd.rd.nx + x;
         const float v = (float)q[c] / N;
@@ -1000,7 +1008,7 @@ extern "C" cap_status cap_plan_run_plain(cap_plan* p, uint64_t seed, uint32_t cy
     CAP_HIP(hipLaunchKernel(p->rollout_one_fn[sl[i].rd.shift ? 1 : 0], dim3(tiles), dim3(p->cfg.block_threads), args,
                             window_lds_bytes(p->cap_words, p->per_tile), s));
     if (sl[i].probs && sl[i].smooth_r == 0) {
-      const unsigned nb = (unsigned)std::min(sl[i].rd.H, 4096);
+      const unsigned nb = (unsigned)std::min(4 * sl[i].rd.H, 4096);
       hipLaunchKernelGGL(plan_normalize_kernel, dim3(nb), dim3(256), 0, s, base, i);
     }
     if (sl[i].probs && sl[i].smooth_r > 0) {
