@@ -158,6 +158,8 @@ class Server:
         human that was within r metres of one of its goals and is now farther
         from all of them gets a uniform belief before the next update (Sec. IV-B).
         The paper specifies neither detector; these are the simplest readings.
+        Both are fixed at construction (with neither, a cycle skips the
+        per-human detection bookkeeping).
         freeze_gc: gc.freeze() once the server is built (see the module notes).
         history: how many of the latest CycleRecords `records` keeps.
         union = (frame, H): every cycle also writes, inside its graph, the
@@ -263,8 +265,9 @@ class Server:
             # one library call for all humans, validated as a whole: a rejected
             # observation leaves every human's state as it was
             self.plan.stage_many([self.slot_of[hid] for hid, _ in seen], [xy for _, xy in seen])
-        for hid, xy in seen:
-            self._detect(hid, xy)
+        if self.stationary is not None or self.goal_departure is not None:
+            for hid, xy in seen:
+                self._detect(hid, xy)
         stream = self.streams[self.cycle % len(self.streams)]
         if self._dep is not None:
             for st in self.streams:
