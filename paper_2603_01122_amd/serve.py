@@ -274,12 +274,12 @@ class Server:
                 st.wait_event(self._dep)
             self._dep = None
         ev = torch.cuda.Event()
-        with torch.cuda.stream(stream):
-            if plain:
-                self.plan.run_plain(self.seed, self.cycle)
-            else:
-                self.plan.run(self.seed, self.cycle)
-            ev.record(stream)
+        # the library takes the stream itself: no switch of torch's current stream
+        if plain:
+            self.plan.run_plain(self.seed, self.cycle, stream)
+        else:
+            self.plan.run(self.seed, self.cycle, stream)
+        ev.record(stream)
         rec = CycleRecord(self.cycle, self.clock() if release is None else release, ev,
                           sorted(self.slot_of), sum(self.req[h].N * self.req[h].H
                                                     for h in self.slot_of))
